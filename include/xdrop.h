@@ -1,0 +1,153 @@
+/*
+ * xdrop.h -- C ABI of libxdrop.so: batched X-drop seed-and-extend of long-read
+ * pairs on one AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (paper, "Related works": BELLA's seed-and-extend with an
+ * X-drop; LOGAN's GPU X-drop over anti-diagonals; "Results": the aligner is a
+ * Needleman-Wunsch / Smith-Waterman recurrence with an X-drop):
+ *
+ *   For each record, read B is oriented (B' = B, or its reverse complement
+ *   when strand = 1), the seed A[pos_a, pos_a+k) vs B'[pos_b', pos_b'+k) is
+ *   scored base by base, and the alignment is extended to the left and to the
+ *   right with an X-drop dynamic programme over anti-diagonals:
+ *     - cell (i,j) of an extension lies on anti-diagonal d = i+j; S(0,0) = 0;
+ *     - a cell is evaluated when one of (i-1,j-1), (i-1,j), (i,j-1) is live;
+ *       its value is the best of S(i-1,j-1)+sigma, S(i-1,j)+gap, S(i,j-1)+gap
+ *       over live predecessors (linear gap, no zero floor);
+ *     - it dies when its value is strictly below T_{d-1} - X, T_{d-1} being
+ *       the best live value on anti-diagonals 0..d-1;
+ *     - the extension stops after two consecutive anti-diagonals without a
+ *       live cell (or at the far corner); its result is the best value T and
+ *       the first cell reaching it (smallest d, then smallest i).
+ *   Batches follow the paper's baseline scheduler ("Method", Baseline): the
+ *   caller hands over one batch of records per call.
+ *
+ * Conventions: every call returns xdrop_status (0 = OK, < 0 = error).  Scores
+ * are exact int32; nothing is approximated.  Reads are ASCII A/C/G/T (either
+ * case).  Coordinates are 0-based, spans half-open.
+ *
+ * Threading: xdrop_batch_submit*, xdrop_batch_wait and xdrop_batch_query may
+ * be called concurrently from many threads on one context (producers).
+ * xdrop_batch_destroy must not race any other call on the same context.
+ */
+#ifndef XDROP_H
+#define XDROP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    XDROP_OK = 0,
+    XDROP_E_INVALID = -1,  /* bad argument or record (nothing was submitted)     */
+    XDROP_E_NOMEM = -2,    /* host or device allocation failed                   */
+    XDROP_E_DEVICE = -3,   /* HIP runtime or kernel error; context is poisoned   */
+    XDROP_E_TIMEOUT = -4,  /* wait timed out; the batch is still running         */
+    XDROP_E_BUSY = -5,     /* admission refused with timeout 0 (back-pressure)   */
+    XDROP_E_STATE = -6     /* unknown or already-consumed ticket, bad ctx state  */
+} xdrop_status;
+
+enum {
+    XDROP_MODE_PERSISTENT = 0, /* whole batch in one graph: bucketed longest-first
+                                  tasks, persistent work-stealing kernels        */
+    XDROP_MODE_PLAIN = 1       /* one launch sequence per 10,000-record chunk, one
+                                  wavefront per extension, no reordering          */
+};
+
+typedef struct xdrop_ctx xdrop_ctx;   /* opaque */
+typedef uint64_t xdrop_ticket;
+
+typedef struct {
+    /* read store, copied and packed at create (caller may free afterwards) */
+    const char *const *reads;     /* n_reads pointers to ASCII bases        */
+    const uint32_t *lengths;      /* n_reads lengths (each <= XDROP_MAX_READ_LEN) */
+    uint32_t n_reads;
+    int32_t device;               /* HIP device ordinal                     */
+    uint32_t mode;                /* XDROP_MODE_*                           */
+    uint32_t max_inflight;        /* batches admitted at once; 0 -> 4       */
+    uint64_t hbm_budget_bytes;    /* device bytes for in-flight batches; 0 -> 8 GiB */
+    const char *tuning_cache;     /* path of the autotuner cache, or NULL   */
+} xdrop_config;
+
+#define XDROP_MAX_READ_LEN (1u << 24)
+#define XDROP_MAX_X (1 << 30)
+
+typedef struct {                  /* 32 bytes, little-endian, packed naturally */
+    uint32_t read_a, read_b;      /* read ids in the store                  */
+    uint32_t pos_a, pos_b;        /* seed start; pos_b in B's own (stored) coordinates */
+    uint16_t k;                   /* seed length, >= 1                      */
+    uint8_t strand;               /* 0: B as stored, 1: B reverse-complemented */
+    uint8_t pad;
+    int32_t x;                    /* drop, 0 <= x <= XDROP_MAX_X            */
+    int16_t match, mismatch, gap; /* match >= 1, mismatch < match, gap <= -1;
+                                     |weights| <= 1024                      */
+    int16_t pad2;
+} xdrop_record;
+
+typedef struct {                  /* 32 bytes */
+    int32_t score;                /* left_score + seed_score + right_score  */
+    int32_t left_score, right_score, seed_score;
+    uint32_t a_begin, a_end;      /* aligned span [a_begin, a_end) of A     */
+    uint32_t b_begin, b_end;      /* span of B' (the reverse-complement frame
+                                     when strand = 1); in B's own frame it is
+                                     [|B| - b_end, |B| - b_begin)            */
+} xdrop_result;
+
+typedef struct {
+    uint64_t records;
+    uint64_t cells;               /* candidate cells evaluated (left + right);
+                                     only filled when cell counting was asked */
+    double queue_ms;              /* submit entry -> admitted               */
+    double device_ms;             /* first kernel start -> last kernel end  */
+    double total_ms;              /* submit entry -> completion             */
+} xdrop_batch_stats;
+
+/* Create a context on cfg->device: packs the reads to 2 bits per base (both
+ * orientations) and uploads them.  Returns XDROP_E_INVALID for a non-ACGT base,
+ * an empty/oversized read or a bad field; *out is set only on XDROP_OK. */
+xdrop_status xdrop_batch_create(const xdrop_config *cfg, xdrop_ctx **out);
+
+/* Submit n host records.  The whole batch is validated first (bad read id,
+ * seed outside a read, k = 0, x out of range, bad weights -> XDROP_E_INVALID,
+ * nothing submitted).  recs is copied before return.  out (n results) and
+ * cells (n uint64, nullable: per-record left+right cell counts) are written
+ * when the batch completes and must stay valid until xdrop_batch_wait returns
+ * XDROP_OK for the ticket.  admit_timeout_us: 0 -> XDROP_E_BUSY when no slot or
+ * HBM budget is free; < 0 -> block until admitted; > 0 -> wait at most that
+ * long, then XDROP_E_BUSY.  n = 0 is allowed (completes immediately). */
+xdrop_status xdrop_batch_submit(xdrop_ctx *c, const xdrop_record *recs, size_t n,
+                                xdrop_result *out, uint64_t *cells,
+                                int64_t admit_timeout_us, xdrop_ticket *ticket);
+
+/* Submit n records that already live in device memory of the context's GPU;
+ * results (and cells, nullable) are written to device memory.  The work is
+ * ordered on `stream` (a hipStream_t; NULL = the context's own stream).
+ * Records are validated on the device: an invalid record makes the ticket's
+ * wait return XDROP_E_INVALID and its result row is zero-filled.  Buffers
+ * must stay valid until wait returns. */
+xdrop_status xdrop_batch_submit_device(xdrop_ctx *c, const xdrop_record *d_recs, size_t n,
+                                       xdrop_result *d_out, uint64_t *d_cells,
+                                       void *stream, xdrop_ticket *ticket);
+
+/* Wait for a ticket.  timeout_us < 0 waits forever, 0 polls.  On XDROP_OK the
+ * ticket is consumed and stats (nullable) is filled.  XDROP_E_TIMEOUT leaves
+ * the ticket outstanding. */
+xdrop_status xdrop_batch_wait(xdrop_ctx *c, xdrop_ticket t, int64_t timeout_us,
+                              xdrop_batch_stats *stats);
+
+/* Drain outstanding batches, then free everything.  NULL is a no-op. */
+xdrop_status xdrop_batch_destroy(xdrop_ctx *c);
+
+/* Human-readable text of a status code (static storage). */
+const char *xdrop_status_string(xdrop_status s);
+
+/* Last error message recorded on the context (or globally when c is NULL). */
+const char *xdrop_last_error(const xdrop_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XDROP_H */

@@ -1,0 +1,738 @@
+// xdrop_capi.cpp -- host runtime of libxdrop.so: read store, validation,
+// admission, per-slot batch pipelines, hipGraph capture, C ABI.
+//
+// One context owns a device-resident 2-bit read store and a pool of "slots".
+// A slot is the set of device and pinned host buffers of one in-flight batch
+// together with its own HIP stream and worker thread.  A submitted batch is
+// admitted when a slot is free and its device footprint fits the HBM budget
+// (growing or re-sizing slots as needed); the slot's worker runs the batch
+// (copy-in, kernels, copy-out) and completes the ticket.  Several slots run at
+// once, so batches that arrive while others are on the GPU overlap on the
+// device: this is the continuous-batching serving loop that replaces the
+// paper's MPI ranks taking turns on the GPU ("Method": One-to-all and
+// One-to-one schedulers).
+//
+// Execution forms ("Method", Baseline: batches of 10,000 pairs fed one at a
+// time):
+//   XDROP_MODE_PLAIN       one launch sequence per 10,000-record chunk, one
+//                          wavefront per extension, no reordering;
+//   XDROP_MODE_PERSISTENT  the whole batch in one captured hipGraph: records
+//                          are classed by drop, bucketed longest-first, and
+//                          persistent work-stealing kernels drain each class.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <fstream>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "xdrop_internal.h"
+
+
+using namespace xd;
+
+namespace {
+
+constexpr uint32_t kPlainChunk = 10000;
+constexpr uint64_t kGuardBases = 512;   // unused bases before and after the store
+
+using clk = std::chrono::steady_clock;
+
+double now_ms()
+{
+    return std::chrono::duration<double, std::milli>(clk::now().time_since_epoch()).count();
+}
+
+std::mutex g_err_mu;
+std::string g_err_text;
+
+void set_global_error(const std::string &s)
+{
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    g_err_text = s;
+}
+
+int8_t base_code(char c)
+{
+    switch (c) {
+    case 'A': case 'a': return 0;
+    case 'C': case 'c': return 1;
+    case 'G': case 'g': return 2;
+    case 'T': case 't': return 3;
+    default: return -1;
+    }
+}
+
+struct Slot;
+
+struct Ticket {
+    uint64_t id = 0;
+    size_t n = 0;
+    bool device = false;
+    const xdrop_record *d_in = nullptr;   // device path input
+    xdrop_result *out = nullptr;          // host or device output
+    uint64_t *cells = nullptr;
+    hipStream_t ustream = nullptr;
+    Slot *slot = nullptr;
+    bool done = false;
+    xdrop_status status = XDROP_OK;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    float dev_ms = 0.f;
+    uint64_t total_cells = 0;
+};
+
+struct Slot {
+    uint32_t cap = 0;
+    size_t bytes = 0;                 // device footprint
+    void *dblock = nullptr;
+    int32_t *scratch = nullptr;       // generic-kernel diagonals
+    uint64_t scratch_stride = 0;
+    uint32_t generic_waves = 0;
+    BatchDev dev{};
+    uint32_t *d_n = nullptr;          // batch size word read by the reset kernel
+    xdrop_record *h_recs = nullptr;   // pinned staging
+    xdrop_result *h_res = nullptr;
+    uint64_t *h_cells = nullptr;
+    uint32_t *h_misc = nullptr;       // [0] = n, [1] = error count
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};   // [count_cells]
+    bool busy = false;
+    std::shared_ptr<Ticket> job;
+    std::thread worker;
+    std::condition_variable cv;
+};
+
+}  // namespace
+
+struct xdrop_ctx {
+    int device = 0;
+    uint32_t mode = XDROP_MODE_PERSISTENT;
+    uint32_t max_inflight = 4;
+    uint64_t budget = 8ull << 30;
+    uint64_t used = 0;
+    int cus = 256;
+
+    // store
+    uint32_t *d_words = nullptr;
+    ReadInfo *d_reads = nullptr;
+    std::vector<uint32_t> h_len;
+    StoreDev st{};
+    uint64_t store_bytes = 0;
+
+    Tuning tune{};
+    std::string tuning_path;
+
+    std::mutex mu;
+    std::condition_variable cv;
+    std::vector<std::unique_ptr<Slot>> slots;
+    std::unordered_map<uint64_t, std::shared_ptr<Ticket>> tickets;
+    uint64_t next_id = 1;
+    bool stop = false;
+    bool poisoned = false;
+    std::string err;
+
+    void fail(const std::string &s)
+    {
+        err = s;
+        set_global_error(s);
+    }
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            throw std::runtime_error(std::string(#expr) + ": " + hipGetErrorString(e_)); \
+        }                                                                                 \
+    } while (0)
+
+Tuning default_tuning()
+{
+    Tuning t{};
+    // start class by drop: the live band of a 15 %-error overlap is about 0.9 X
+    // cells wide on average and up to ~1.45 X at its widest.
+    const int32_t lim[kWindowClasses] = {24, 60, 100, 150, 0x7fffffff};
+    for (int q = 0; q < kWindowClasses; ++q) t.x_class_limit[q] = lim[q];
+    t.waves_per_cu = 32;
+    t.buckets = 1;
+    t.generic_waves = 256;
+    return t;
+}
+
+bool load_tuning(const std::string &path, Tuning &t)
+{
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string key;
+    while (f >> key) {
+        if (key == "x_class_limit") {
+            for (int q = 0; q < kWindowClasses; ++q) f >> t.x_class_limit[q];
+        } else if (key == "waves_per_cu") {
+            f >> t.waves_per_cu;
+        } else if (key == "buckets") {
+            f >> t.buckets;
+        } else if (key == "generic_waves") {
+            f >> t.generic_waves;
+        } else {
+            std::string rest;
+            std::getline(f, rest);
+        }
+    }
+    return true;
+}
+
+bool validate_host(const xdrop_ctx *c, const xdrop_record &R, std::string &why)
+{
+    const uint32_t nr = (uint32_t)c->h_len.size();
+    if (R.read_a >= nr || R.read_b >= nr) { why = "read id out of range"; return false; }
+    const uint64_t la = c->h_len[R.read_a], lb = c->h_len[R.read_b];
+    if (R.k < 1) { why = "k = 0"; return false; }
+    if ((uint64_t)R.pos_a + R.k > la || (uint64_t)R.pos_b + R.k > lb) { why = "seed outside a read"; return false; }
+    if (R.strand > 1) { why = "strand must be 0 or 1"; return false; }
+    if (R.x < 0 || R.x > XDROP_MAX_X) { why = "x out of range"; return false; }
+    if (R.match < 1 || R.match > 1024 || R.mismatch >= R.match || R.mismatch < -1024 || R.gap > -1 ||
+        R.gap < -1024) {
+        why = "bad weights";
+        return false;
+    }
+    const int64_t w = (int64_t)R.match - R.mismatch - R.gap;
+    if (w * (int64_t)(la + lb) > (1ll << 29)) { why = "weights too large for these read lengths"; return false; }
+    return true;
+}
+
+size_t slot_bytes(uint32_t cap)
+{
+    const size_t n = cap;
+    size_t b = 0;
+    auto add = [&](size_t x) { b += (x + 255) & ~size_t(255); };
+    add(n * sizeof(xdrop_record));
+    add(n * sizeof(xdrop_result));
+    add(n * sizeof(uint64_t));
+    add(n * sizeof(int32_t));
+    add(n);
+    add(2 * n * sizeof(TaskOut));
+    add((size_t)kNumClasses * 2 * n * sizeof(uint32_t));   // qbuf
+    add((size_t)kNumClasses * 2 * n * sizeof(uint32_t));   // qkey
+    add(CtrLayout::kWords * sizeof(uint32_t) + 64);
+    add((size_t)kNumClasses * kNumBuckets * sizeof(uint32_t));
+    return b;
+}
+
+void free_slot_buffers(Slot &s)
+{
+    for (auto &g : s.graph)
+        if (g) { hipGraphExecDestroy(g); g = nullptr; }
+    if (s.dblock) hipFree(s.dblock);
+    if (s.scratch) hipFree(s.scratch);
+    if (s.h_recs) hipHostFree(s.h_recs);
+    if (s.h_res) hipHostFree(s.h_res);
+    if (s.h_cells) hipHostFree(s.h_cells);
+    if (s.h_misc) hipHostFree(s.h_misc);
+    s.dblock = nullptr; s.scratch = nullptr; s.h_recs = nullptr; s.h_res = nullptr; s.h_cells = nullptr;
+    s.h_misc = nullptr;
+    s.cap = 0;
+    s.bytes = 0;
+}
+
+void alloc_slot_buffers(xdrop_ctx *c, Slot &s, uint32_t cap)
+{
+    s.cap = cap;
+    s.bytes = slot_bytes(cap);
+    HIP_TRY(hipMalloc(&s.dblock, s.bytes));
+    char *p = (char *)s.dblock;
+    auto take = [&](size_t x) {
+        char *q = p;
+        p += (x + 255) & ~size_t(255);
+        return (void *)q;
+    };
+    const size_t n = cap;
+    s.dev.recs = (const xdrop_record *)take(n * sizeof(xdrop_record));
+    s.dev.res = (xdrop_result *)take(n * sizeof(xdrop_result));
+    s.dev.cells = (uint64_t *)take(n * sizeof(uint64_t));
+    s.dev.seed = (int32_t *)take(n * sizeof(int32_t));
+    s.dev.valid = (uint8_t *)take(n);
+    s.dev.tout = (TaskOut *)take(2 * n * sizeof(TaskOut));
+    s.dev.qbuf = (uint32_t *)take((size_t)kNumClasses * 2 * n * sizeof(uint32_t));
+    s.dev.qkey = (uint32_t *)take((size_t)kNumClasses * 2 * n * sizeof(uint32_t));
+    s.dev.ctr = (uint32_t *)take(CtrLayout::kWords * sizeof(uint32_t) + 64);
+    s.d_n = s.dev.ctr + CtrLayout::kWords;
+    s.dev.bucket_hist = (uint32_t *)take((size_t)kNumClasses * kNumBuckets * sizeof(uint32_t));
+    s.dev.cap = cap;
+    // generic-kernel scratch: three anti-diagonals per wavefront
+    s.generic_waves = (uint32_t)((std::max(4, c->tune.generic_waves) + 3) / 4 * 4);   // whole blocks of 4
+    s.scratch_stride = ((uint64_t)c->st.max_len + 2 + 63) & ~uint64_t(63);
+    HIP_TRY(hipMalloc(&s.scratch, (size_t)s.generic_waves * 3 * s.scratch_stride * sizeof(int32_t)));
+    s.bytes += (size_t)s.generic_waves * 3 * s.scratch_stride * sizeof(int32_t);
+    HIP_TRY(hipHostMalloc((void **)&s.h_recs, n * sizeof(xdrop_record), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void **)&s.h_res, n * sizeof(xdrop_result), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void **)&s.h_cells, n * sizeof(uint64_t), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void **)&s.h_misc, 64, hipHostMallocDefault));
+}
+
+size_t slot_footprint(const xdrop_ctx *c, uint32_t cap)
+{
+    const uint64_t stride = ((uint64_t)c->st.max_len + 2 + 63) & ~uint64_t(63);
+    return slot_bytes(cap) + (size_t)((std::max(4, c->tune.generic_waves) + 3) / 4 * 4) * 3 * stride * sizeof(int32_t);
+}
+
+uint32_t round_cap(size_t n)
+{
+    uint32_t c = 1024;
+    while (c < n) c <<= 1;
+    return c;
+}
+
+// Kernel sequence of one batch (or chunk) on `s`.  `b` may be a view into the
+// slot buffers (plain chunks); n_src non-null means "read n from device".
+void enqueue_kernels(xdrop_ctx *c, Slot &sl, const BatchDev &b, uint32_t n, const uint32_t *n_src, bool persistent,
+                     bool count, hipStream_t s)
+{
+    launch_reset_n(b, n_src, n, s);
+    const bool stage = persistent && c->tune.buckets > 0;
+    launch_prep(b, c->st, c->tune, n, stage, s);
+    if (stage) launch_bucket(b, c->st, n, s);
+    const uint32_t resident = (uint32_t)c->cus * (uint32_t)std::max(1, c->tune.waves_per_cu);
+    for (int q = 0; q < kWindowClasses; ++q) {
+        uint32_t waves = persistent ? resident : std::max<uint32_t>(2 * n, 4);
+        launch_window(q, b, c->st, waves, count, s);
+    }
+    launch_generic(b, c->st, sl.scratch, sl.scratch_stride, sl.generic_waves, count, s);
+    launch_finalize(b, c->st, n, s);
+}
+
+hipGraphExec_t get_graph(xdrop_ctx *c, Slot &sl, bool count)
+{
+    hipGraphExec_t &g = sl.graph[count ? 1 : 0];
+    if (g) return g;
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal));
+    enqueue_kernels(c, sl, sl.dev, sl.cap, sl.d_n, true, count, sl.stream);
+    HIP_TRY(hipStreamEndCapture(sl.stream, &graph));
+    HIP_TRY(hipGraphInstantiate(&g, graph, nullptr, nullptr, 0));
+    hipGraphDestroy(graph);
+    return g;
+}
+
+void run_batch(xdrop_ctx *c, Slot &sl, Ticket &t)
+{
+    const uint32_t n = (uint32_t)t.n;
+    hipStream_t s = (t.device && t.ustream) ? t.ustream : sl.stream;
+    const bool count = t.cells != nullptr;
+    HIP_TRY(hipSetDevice(c->device));
+    if (t.device)
+        HIP_TRY(hipMemcpyAsync((void *)sl.dev.recs, t.d_in, (size_t)n * sizeof(xdrop_record), hipMemcpyDeviceToDevice, s));
+    else
+        HIP_TRY(hipMemcpyAsync((void *)sl.dev.recs, sl.h_recs, (size_t)n * sizeof(xdrop_record), hipMemcpyHostToDevice, s));
+    sl.h_misc[0] = n;
+    HIP_TRY(hipMemcpyAsync(sl.d_n, sl.h_misc, sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(sl.ev0, s));
+    if (c->mode == XDROP_MODE_PERSISTENT) {
+        HIP_TRY(hipGraphLaunch(get_graph(c, sl, count), s));
+    } else {
+        HIP_TRY(hipMemsetAsync(sl.d_n + 1, 0, sizeof(uint32_t), s));
+        for (uint32_t off = 0; off < n; off += kPlainChunk) {
+            const uint32_t m = std::min(kPlainChunk, n - off);
+            BatchDev v = sl.dev;
+            v.recs += off; v.res += off; v.cells += off; v.seed += off; v.valid += off; v.tout += 2 * (size_t)off;
+            enqueue_kernels(c, sl, v, m, nullptr, false, count, s);
+            // chunk errors accumulate in the slot's error word
+            launch_accum_errors(v, sl.d_n + 1, s);
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(sl.ev1, s));
+    if (t.device) {
+        HIP_TRY(hipMemcpyAsync(t.out, sl.dev.res, (size_t)n * sizeof(xdrop_result), hipMemcpyDeviceToDevice, s));
+        if (count) HIP_TRY(hipMemcpyAsync(t.cells, sl.dev.cells, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+    } else {
+        HIP_TRY(hipMemcpyAsync(sl.h_res, sl.dev.res, (size_t)n * sizeof(xdrop_result), hipMemcpyDeviceToHost, s));
+        if (count) HIP_TRY(hipMemcpyAsync(sl.h_cells, sl.dev.cells, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+    }
+    const uint32_t *err_src = c->mode == XDROP_MODE_PERSISTENT ? sl.dev.ctr + CtrLayout::kErrors : sl.d_n + 1;
+    HIP_TRY(hipMemcpyAsync(sl.h_misc + 1, err_src, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(sl.ev2, s));
+    HIP_TRY(hipEventSynchronize(sl.ev2));
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, sl.ev0, sl.ev1);
+    t.dev_ms = ms;
+    const uint32_t errors = sl.h_misc[1];
+    if (!t.device) {
+        std::memcpy(t.out, sl.h_res, (size_t)n * sizeof(xdrop_result));
+        if (count) std::memcpy(t.cells, sl.h_cells, (size_t)n * 8);
+    }
+    if (count) {
+        uint64_t tot = 0;
+        if (t.device) {
+            // per-record counts stay on the device; stats carry no total
+        } else {
+            for (uint32_t i = 0; i < n; ++i) tot += t.cells[i];
+        }
+        t.total_cells = tot;
+    }
+    t.status = errors ? XDROP_E_INVALID : XDROP_OK;
+}
+
+void slot_worker(xdrop_ctx *c, Slot *sl)
+{
+    hipSetDevice(c->device);
+    std::unique_lock<std::mutex> lk(c->mu);
+    for (;;) {
+        sl->cv.wait(lk, [&] { return c->stop || sl->job != nullptr; });
+        if (sl->job == nullptr && c->stop) break;
+        std::shared_ptr<Ticket> t = sl->job;
+        lk.unlock();
+        xdrop_status st = XDROP_OK;
+        std::string msg;
+        if (t->n > 0) {
+            try {
+                run_batch(c, *sl, *t);
+                st = t->status;
+            } catch (const std::exception &e) {
+                st = XDROP_E_DEVICE;
+                msg = e.what();
+            }
+        }
+        lk.lock();
+        if (st == XDROP_E_DEVICE) {
+            c->poisoned = true;
+            c->fail(msg);
+            for (auto &kv : c->tickets)
+                if (!kv.second->done) kv.second->status = XDROP_E_DEVICE;
+        }
+        t->status = c->poisoned ? XDROP_E_DEVICE : st;
+        t->t_done = now_ms();
+        t->done = true;
+        sl->job = nullptr;
+        sl->busy = false;
+        c->cv.notify_all();
+    }
+}
+
+Slot *new_slot(xdrop_ctx *c)
+{
+    auto s = std::make_unique<Slot>();
+    HIP_TRY(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreate(&s->ev0));
+    HIP_TRY(hipEventCreate(&s->ev1));
+    HIP_TRY(hipEventCreateWithFlags(&s->ev2, hipEventBlockingSync));
+    Slot *raw = s.get();
+    raw->worker = std::thread(slot_worker, c, raw);
+    c->slots.push_back(std::move(s));
+    return raw;
+}
+
+// Admission (called with c->mu held): a free slot with enough capacity, or a
+// new / re-sized slot when the HBM budget allows.  Returns nullptr if none.
+Slot *try_admit(xdrop_ctx *c, size_t n)
+{
+    Slot *best = nullptr;
+    for (auto &s : c->slots)
+        if (!s->busy && s->cap >= n && (!best || s->cap < best->cap)) best = s.get();
+    if (best) return best;
+    const uint32_t cap = round_cap(n);
+    const size_t need = slot_footprint(c, cap);
+    // a new slot
+    if (c->slots.size() < c->max_inflight && c->used + need <= c->budget) {
+        Slot *s = new_slot(c);
+        alloc_slot_buffers(c, *s, cap);
+        c->used += s->bytes;
+        return s;
+    }
+    // re-size the largest idle slot
+    Slot *idle = nullptr;
+    for (auto &s : c->slots)
+        if (!s->busy && (!idle || s->cap > idle->cap)) idle = s.get();
+    if (idle && c->used - idle->bytes + need <= c->budget) {
+        c->used -= idle->bytes;
+        free_slot_buffers(*idle);
+        alloc_slot_buffers(c, *idle, cap);
+        c->used += idle->bytes;
+        return idle;
+    }
+    return nullptr;
+}
+
+xdrop_status submit_common(xdrop_ctx *c, std::shared_ptr<Ticket> t, const xdrop_record *host_recs,
+                           int64_t admit_timeout_us, xdrop_ticket *ticket)
+{
+    t->t_submit = now_ms();
+    std::unique_lock<std::mutex> lk(c->mu);
+    if (c->poisoned) return XDROP_E_DEVICE;
+    t->id = c->next_id++;
+    if (t->n == 0) {
+        t->done = true;
+        t->t_admit = t->t_done = now_ms();
+        c->tickets[t->id] = t;
+        *ticket = t->id;
+        return XDROP_OK;
+    }
+    if (slot_footprint(c, round_cap(t->n)) > c->budget) {
+        c->fail("batch does not fit the HBM budget even alone");
+        return XDROP_E_NOMEM;
+    }
+    const auto deadline = clk::now() + std::chrono::microseconds(admit_timeout_us > 0 ? admit_timeout_us : 0);
+    Slot *sl = nullptr;
+    for (;;) {
+        if (c->poisoned) return XDROP_E_DEVICE;
+        try {
+            sl = try_admit(c, t->n);
+        } catch (const std::exception &e) {
+            c->fail(e.what());
+            return XDROP_E_NOMEM;
+        }
+        if (sl) break;
+        if (admit_timeout_us == 0) return XDROP_E_BUSY;
+        if (admit_timeout_us < 0) {
+            c->cv.wait(lk);
+        } else if (c->cv.wait_until(lk, deadline) == std::cv_status::timeout) {
+            sl = try_admit(c, t->n);
+            if (!sl) return XDROP_E_BUSY;
+            break;
+        }
+    }
+    sl->busy = true;
+    t->slot = sl;
+    t->t_admit = now_ms();
+    c->tickets[t->id] = t;
+    *ticket = t->id;
+    if (host_recs) {
+        lk.unlock();
+        std::memcpy(sl->h_recs, host_recs, t->n * sizeof(xdrop_record));
+        lk.lock();
+    }
+    sl->job = t;
+    sl->cv.notify_one();
+    return XDROP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *xdrop_status_string(xdrop_status s)
+{
+    switch (s) {
+    case XDROP_OK: return "ok";
+    case XDROP_E_INVALID: return "invalid argument or record";
+    case XDROP_E_NOMEM: return "out of memory";
+    case XDROP_E_DEVICE: return "device error";
+    case XDROP_E_TIMEOUT: return "timed out";
+    case XDROP_E_BUSY: return "admission refused (busy)";
+    case XDROP_E_STATE: return "bad ticket or context state";
+    default: return "unknown status";
+    }
+}
+
+const char *xdrop_last_error(const xdrop_ctx *c)
+{
+    if (c) return c->err.c_str();
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    return g_err_text.c_str();
+}
+
+xdrop_status xdrop_batch_create(const xdrop_config *cfg, xdrop_ctx **out)
+{
+    if (!cfg || !out) return XDROP_E_INVALID;
+    if (cfg->n_reads == 0 || !cfg->reads || !cfg->lengths) {
+        set_global_error("empty read store");
+        return XDROP_E_INVALID;
+    }
+    if (cfg->mode > XDROP_MODE_PLAIN) {
+        set_global_error("unknown mode");
+        return XDROP_E_INVALID;
+    }
+    std::unique_ptr<xdrop_ctx> c(new xdrop_ctx);
+    c->device = cfg->device;
+    c->mode = cfg->mode;
+    c->max_inflight = cfg->max_inflight ? cfg->max_inflight : 4;
+    c->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (8ull << 30);
+    c->tune = default_tuning();
+    if (cfg->tuning_cache) {
+        c->tuning_path = cfg->tuning_cache;
+        load_tuning(c->tuning_path, c->tune);
+    }
+    // pack the store: fwd and reverse complement of every read, each starting
+    // on a word boundary, 2 bits per base
+    const uint32_t nr = cfg->n_reads;
+    c->h_len.assign(cfg->lengths, cfg->lengths + nr);
+    std::vector<ReadInfo> info(nr);
+    uint64_t pos = kGuardBases;
+    uint32_t max_len = 0;
+    for (uint32_t r = 0; r < nr; ++r) {
+        const uint32_t L = cfg->lengths[r];
+        if (L == 0 || L > XDROP_MAX_READ_LEN || !cfg->reads[r]) {
+            set_global_error("read " + std::to_string(r) + ": empty or too long");
+            return XDROP_E_INVALID;
+        }
+        max_len = std::max(max_len, L);
+        info[r].len = L;
+        info[r].fwd = pos;
+        pos += ((uint64_t)L + 15) & ~uint64_t(15);
+        info[r].rc = pos;
+        pos += ((uint64_t)L + 15) & ~uint64_t(15);
+    }
+    const uint64_t total_bases = pos + kGuardBases;
+    const uint64_t nwords = (total_bases + 15) / 16 + 4;
+    std::vector<uint32_t> words(nwords, 0u);
+    std::atomic<int64_t> bad{-1};
+    {
+        const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::vector<std::thread> th;
+        for (unsigned w = 0; w < nt; ++w) {
+            th.emplace_back([&, w] {
+                for (uint32_t r = w; r < nr; r += nt) {
+                    const char *s = cfg->reads[r];
+                    const uint32_t L = info[r].len;
+                    for (uint32_t p = 0; p < L; ++p) {
+                        const int8_t v = base_code(s[p]);
+                        if (v < 0) {
+                            bad = r;
+                            return;
+                        }
+                        const uint64_t f = info[r].fwd + p;
+                        const uint64_t q = info[r].rc + (L - 1 - p);
+                        words[f >> 4] |= (uint32_t)v << ((f & 15) * 2);
+                        words[q >> 4] |= (uint32_t)(3 - v) << ((q & 15) * 2);
+                    }
+                }
+            });
+        }
+        for (auto &t : th) t.join();
+    }
+    if (bad >= 0) {
+        set_global_error("read " + std::to_string((long long)bad) + ": non-ACGT base");
+        return XDROP_E_INVALID;
+    }
+    try {
+        HIP_TRY(hipSetDevice(c->device));
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, c->device));
+        c->cus = prop.multiProcessorCount;
+        HIP_TRY(hipMalloc(&c->d_words, nwords * sizeof(uint32_t)));
+        HIP_TRY(hipMalloc(&c->d_reads, (size_t)nr * sizeof(ReadInfo)));
+        HIP_TRY(hipMemcpy(c->d_words, words.data(), nwords * sizeof(uint32_t), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->d_reads, info.data(), (size_t)nr * sizeof(ReadInfo), hipMemcpyHostToDevice));
+    } catch (const std::exception &e) {
+        set_global_error(e.what());
+        if (c->d_words) hipFree(c->d_words);
+        if (c->d_reads) hipFree(c->d_reads);
+        return XDROP_E_DEVICE;
+    }
+    c->store_bytes = nwords * 4 + (uint64_t)nr * sizeof(ReadInfo);
+    c->st.words = c->d_words;
+    c->st.reads = c->d_reads;
+    c->st.n_reads = nr;
+    c->st.max_len = max_len;
+    c->st.max_base = (int64_t)(nwords - 4) * 16 - 48;
+    *out = c.release();
+    return XDROP_OK;
+}
+
+xdrop_status xdrop_batch_submit(xdrop_ctx *c, const xdrop_record *recs, size_t n, xdrop_result *out,
+                                uint64_t *cells, int64_t admit_timeout_us, xdrop_ticket *ticket)
+{
+    if (!c || !ticket || (n && (!recs || !out))) return XDROP_E_INVALID;
+    if (n > 0x7fffffffu) {
+        c->fail("batch too large");
+        return XDROP_E_INVALID;
+    }
+    std::string why;
+    for (size_t i = 0; i < n; ++i) {
+        if (!validate_host(c, recs[i], why)) {
+            std::lock_guard<std::mutex> lk(c->mu);
+            c->fail("record " + std::to_string(i) + ": " + why);
+            return XDROP_E_INVALID;
+        }
+    }
+    auto t = std::make_shared<Ticket>();
+    t->n = n;
+    t->out = out;
+    t->cells = cells;
+    return submit_common(c, t, recs, admit_timeout_us, ticket);
+}
+
+xdrop_status xdrop_batch_submit_device(xdrop_ctx *c, const xdrop_record *d_recs, size_t n, xdrop_result *d_out,
+                                       uint64_t *d_cells, void *stream, xdrop_ticket *ticket)
+{
+    if (!c || !ticket || (n && (!d_recs || !d_out))) return XDROP_E_INVALID;
+    if (n > 0x7fffffffu) return XDROP_E_INVALID;
+    auto t = std::make_shared<Ticket>();
+    t->n = n;
+    t->device = true;
+    t->d_in = d_recs;
+    t->out = d_out;
+    t->cells = d_cells;
+    t->ustream = (hipStream_t)stream;
+    return submit_common(c, t, nullptr, -1, ticket);
+}
+
+xdrop_status xdrop_batch_wait(xdrop_ctx *c, xdrop_ticket id, int64_t timeout_us, xdrop_batch_stats *stats)
+{
+    if (!c) return XDROP_E_INVALID;
+    std::unique_lock<std::mutex> lk(c->mu);
+    auto it = c->tickets.find(id);
+    if (it == c->tickets.end()) return XDROP_E_STATE;
+    std::shared_ptr<Ticket> t = it->second;
+    if (!t->done) {
+        if (timeout_us == 0) return XDROP_E_TIMEOUT;
+        if (timeout_us < 0) {
+            c->cv.wait(lk, [&] { return t->done; });
+        } else if (!c->cv.wait_for(lk, std::chrono::microseconds(timeout_us), [&] { return t->done; })) {
+            return XDROP_E_TIMEOUT;
+        }
+    }
+    c->tickets.erase(id);
+    if (stats) {
+        stats->records = t->n;
+        stats->cells = t->total_cells;
+        stats->queue_ms = t->t_admit - t->t_submit;
+        stats->device_ms = t->dev_ms;
+        stats->total_ms = t->t_done - t->t_submit;
+    }
+    return t->status;
+}
+
+xdrop_status xdrop_batch_destroy(xdrop_ctx *c)
+{
+    if (!c) return XDROP_OK;
+    {
+        std::unique_lock<std::mutex> lk(c->mu);
+        c->cv.wait(lk, [&] {
+            for (auto &s : c->slots)
+                if (s->busy) return false;
+            return true;
+        });
+        c->stop = true;
+        for (auto &s : c->slots) s->cv.notify_all();
+    }
+    for (auto &s : c->slots)
+        if (s->worker.joinable()) s->worker.join();
+    hipSetDevice(c->device);
+    for (auto &s : c->slots) {
+        free_slot_buffers(*s);
+        if (s->ev0) hipEventDestroy(s->ev0);
+        if (s->ev1) hipEventDestroy(s->ev1);
+        if (s->ev2) hipEventDestroy(s->ev2);
+        if (s->stream) hipStreamDestroy(s->stream);
+    }
+    if (c->d_words) hipFree(c->d_words);
+    if (c->d_reads) hipFree(c->d_reads);
+    delete c;
+    return XDROP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// xdrop_internal.h -- structures shared by the HIP kernels and the host runtime
+// of libxdrop.so.  Not part of the public ABI (include/xdrop.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/xdrop.h"
+
+namespace xd {
+
+// One read of the device store.  Both orientations are packed 2 bits per base,
+// 16 bases per uint32 (base p of the store sits in word p >> 4, bits
+// 2*(p & 15)); fwd/rc are global base indices of the first base.
+struct ReadInfo {
+    uint64_t fwd;
+    uint64_t rc;
+    uint32_t len;
+    uint32_t pad;
+};
+
+// Result of one extension (task).  Task t belongs to record t >> 1; t & 1 is
+// the side (0 = left, 1 = right).
+struct TaskOut {
+    int32_t score;
+    int32_t i, j;
+    uint32_t status;   // 0 = done
+    uint64_t cells;
+};
+
+enum : uint32_t { kStatusDone = 0, kStatusOverflow = 1 };
+
+// Extension kernels, by band window.  Class q < kWindowClasses runs the
+// register-window kernel with kWindowC[q] cells per lane (window 64*C); the
+// last class is the unbounded global-memory kernel.
+constexpr int kWindowClasses = 5;
+constexpr int kWindowC[kWindowClasses] = {1, 2, 3, 4, 16};
+constexpr int kNumClasses = kWindowClasses + 1;
+constexpr int kGenericClass = kWindowClasses;
+constexpr int kNumBuckets = 64;
+
+// Device buffers of one batch (all device pointers).
+struct BatchDev {
+    const xdrop_record *recs;
+    xdrop_result *res;
+    uint64_t *cells;          // nullable, per record
+    int32_t *seed;            // per record
+    uint8_t *valid;           // per record
+    TaskOut *tout;            // 2 per record
+    uint32_t *qbuf;           // kNumClasses queues of capacity 2*cap (task ids)
+    uint32_t *qkey;           // unsorted queue staging: (task id) per class, capacity 2*cap
+    uint32_t *ctr;            // counters, see CtrLayout
+    uint32_t *bucket_hist;    // kNumClasses * kNumBuckets
+    uint32_t cap;             // record capacity of the buffers
+};
+
+// Counter block layout (uint32 words).
+struct CtrLayout {
+    static constexpr int kCount = 0;                       // per class: queue length
+    static constexpr int kHead = kNumClasses;              // per class: next task to fetch
+    static constexpr int kStage = 2 * kNumClasses;         // per class: staging length (bucketing)
+    static constexpr int kErrors = 3 * kNumClasses;        // invalid records
+    static constexpr int kN = 3 * kNumClasses + 1;         // record count of the batch
+    static constexpr int kWords = 3 * kNumClasses + 2;
+};
+
+struct StoreDev {
+    const uint32_t *words;    // packed store, with guard words at both ends
+    const ReadInfo *reads;
+    uint32_t n_reads;
+    uint32_t max_len;
+    int64_t max_base;         // largest base index a loader may touch
+};
+
+// Tunable launch parameters (the autotuner picks them).
+struct Tuning {
+    int32_t x_class_limit[kWindowClasses];  // X <= limit -> start in that class
+    int32_t waves_per_cu;                   // persistent grid size per class kernel
+    int32_t buckets;                        // 0: no length bucketing
+    int32_t generic_waves;                  // grid of the unbounded kernel
+};
+
+// Kernel launchers (xdrop_kernels.hip).  All are asynchronous on `s`.
+// Zero the batch counters; n comes from *n_src (device) when non-null, else n_imm.
+void launch_reset_n(const BatchDev &b, const uint32_t *n_src, uint32_t n_imm, hipStream_t s);
+void launch_accum_errors(const BatchDev &b, uint32_t *acc, hipStream_t s);
+void launch_prep(const BatchDev &b, const StoreDev &st, const Tuning &tu, uint32_t n,
+                 bool stage, hipStream_t s);
+void launch_bucket(const BatchDev &b, const StoreDev &st, uint32_t n, hipStream_t s);
+void launch_window(int cls, const BatchDev &b, const StoreDev &st, uint32_t grid_waves,
+                   bool count_cells, hipStream_t s);
+void launch_generic(const BatchDev &b, const StoreDev &st, int32_t *scratch, uint64_t scratch_stride,
+                    uint32_t grid_waves, bool count_cells, hipStream_t s);
+void launch_finalize(const BatchDev &b, const StoreDev &st, uint32_t n, hipStream_t s);
+
+}  // namespace xd

@@ -1,0 +1,682 @@
+// xdrop_kernels.hip -- gfx950 kernels of batched X-drop seed-and-extend.
+//
+// Method (paper, "Related works": BELLA's seed-and-extend scored with an
+// X-drop; LOGAN computes the X-drop table anti-diagonal by anti-diagonal
+// because the cells of one anti-diagonal are independent; "Results": the
+// aligner is Needleman-Wunsch / Smith-Waterman with an X-drop).  The exact
+// rules (live predecessors, strict drop test against the best score of the
+// previous anti-diagonals, two dead anti-diagonals to stop, first-reached end
+// cell) are stated in include/xdrop.h.
+//
+// Layout on the device:
+//   * reads: 2 bits per base, both orientations, in one word array;
+//   * one wavefront runs one extension (task); all control is wave-uniform
+//     and lives in SGPRs;
+//   * window kernel: the live band of three consecutive anti-diagonals is
+//     held in VGPRs, 64 lanes x C cells, indexed by slot s = C*lane + r with
+//     i = o_d + s and o_d = base + floor(d/2).  With that origin the diagonal
+//     predecessor of a cell sits in the same slot two anti-diagonals back and
+//     the two gap predecessors are slots (s, s+1) on even d and (s-1, s) on
+//     odd d, so one DPP wave shift per anti-diagonal feeds the recurrence;
+//   * values are stored as Z = S + |gap| * d, which removes the gap add from
+//     the recurrence; the thresholds move by |gap| per anti-diagonal;
+//   * work proceeds in blocks of U (odd, even) anti-diagonal pairs; between
+//     blocks the band is re-centred, its growth bound (one slot per pair on
+//     each side) guarantees that no candidate leaves the window inside a
+//     block, and a band that no longer fits escalates the task to a wider
+//     class;
+//   * generic kernel: three anti-diagonals in global memory, any band width.
+#include <hip/hip_runtime.h>
+
+#include "xdrop_internal.h"
+
+namespace xd {
+
+namespace {
+
+constexpr int NEG = -(1 << 30) - (1 << 20);   // dead / outside the table
+constexpr int NEG_HALF = -(1 << 29);          // anything below is "no live predecessor"
+constexpr int UMAX = 16;                      // anti-diagonal pairs per block (max)
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Wave-uniform fetch-and-add of `v` (the value of lane 0).  Every lane takes
+// part (the others add 0) so that no lane-dependent branch surrounds the
+// atomic: lane-divergent control flow next to cross-lane operations lets the
+// compiler split a loop so that some lanes re-enter it without the others.
+__device__ __forceinline__ uint32_t wave_fetch_add(uint32_t *p, uint32_t v)
+{
+    const uint32_t old = atomicAdd(p, (threadIdx.x & 63) == 0 ? v : 0u);
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)old);
+}
+
+__device__ __forceinline__ uint32_t code_at(const uint32_t *__restrict__ W, uint64_t p)
+{
+    return (W[p >> 4] >> ((p & 15) * 2)) & 3u;
+}
+
+// 32 codes starting at base p (clamped into the store), code t at bits 2t.
+__device__ __forceinline__ uint64_t load32(const uint32_t *__restrict__ W, int64_t p, int64_t maxp)
+{
+    p = p < 0 ? 0 : (p > maxp ? maxp : p);
+    const uint64_t w = (uint64_t)p >> 4;
+    const uint32_t sh = (uint32_t)(p & 15) * 2u;
+    const uint32_t w0 = W[w], w1 = W[w + 1], w2 = W[w + 2];
+    const uint32_t lo = __builtin_amdgcn_alignbit(w1, w0, sh);
+    const uint32_t hi = __builtin_amdgcn_alignbit(w2, w1, sh);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+struct Geo {
+    uint64_t abase, bbase;
+    int32_t m, n;
+};
+
+// Orientation of one extension.  Both sequences are read forwards from the
+// store: the right extension reads A and B' after the seed; the left
+// extension reads the reverse complements of A and B' from the mirrored seed
+// start.  Complementing both sides keeps every match/mismatch decision.
+__device__ __forceinline__ Geo task_geo(const xdrop_record &R, const ReadInfo *__restrict__ ri, int side)
+{
+    const ReadInfo A = ri[R.read_a], B = ri[R.read_b];
+    const uint32_t k = R.k;
+    const uint32_t pb = R.strand ? B.len - R.pos_b - k : R.pos_b;
+    Geo g;
+    if (side) {
+        g.m = (int32_t)(A.len - R.pos_a - k);
+        g.n = (int32_t)(B.len - pb - k);
+        g.abase = A.fwd + R.pos_a + k;
+        g.bbase = (R.strand ? B.rc : B.fwd) + pb + k;
+    } else {
+        g.m = (int32_t)R.pos_a;
+        g.n = (int32_t)pb;
+        g.abase = A.rc + (A.len - R.pos_a);
+        g.bbase = (R.strand ? B.fwd : B.rc) + (B.len - pb);
+    }
+    return g;
+}
+
+__device__ __forceinline__ uint64_t uni64(uint64_t x)
+{
+    return ((uint64_t)(uint32_t)uni((int)(x >> 32)) << 32) | (uint32_t)uni((int)(uint32_t)x);
+}
+
+// A task as wave-uniform scalars: the record and the geometry of one side.
+struct Task {
+    Geo g;
+    int x, ma, mi, gap;
+};
+
+__device__ __forceinline__ Task load_task(const xdrop_record *__restrict__ recs, const ReadInfo *__restrict__ ri,
+                                          uint32_t t)
+{
+    const xdrop_record R = recs[t >> 1];
+    Geo g = task_geo(R, ri, (int)(t & 1));
+    Task k;
+    k.g.abase = uni64(g.abase);
+    k.g.bbase = uni64(g.bbase);
+    k.g.m = uni(g.m);
+    k.g.n = uni(g.n);
+    k.x = uni(R.x);
+    k.ma = uni(R.match);
+    k.mi = uni(R.mismatch);
+    k.gap = uni(R.gap);
+    return k;
+}
+
+__device__ __forceinline__ bool record_ok(const xdrop_record &R, const StoreDev &st)
+{
+    if (R.read_a >= st.n_reads || R.read_b >= st.n_reads) return false;
+    const uint32_t la = st.reads[R.read_a].len, lb = st.reads[R.read_b].len;
+    if (R.k < 1 || (uint64_t)R.pos_a + R.k > la || (uint64_t)R.pos_b + R.k > lb) return false;
+    if (R.strand > 1 || R.x < 0 || R.x > XDROP_MAX_X) return false;
+    if (R.match < 1 || R.match > 1024 || R.mismatch >= R.match || R.mismatch < -1024 ||
+        R.gap > -1 || R.gap < -1024)
+        return false;
+    const int64_t w = (int64_t)R.match - R.mismatch - R.gap;
+    if (w * ((int64_t)la + lb) > (1ll << 29)) return false;
+    return true;
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ int bucket_of(uint32_t key)
+{
+    // quarter-octave buckets of the expected extension length, longest first
+    const uint32_t k = key + 1;
+    const int lg = 31 - __clz(k);
+    const int frac = lg >= 2 ? (int)((k >> (lg - 2)) & 3u) : 0;
+    int b = lg * 4 + frac;
+    b = b > kNumBuckets - 1 ? kNumBuckets - 1 : b;
+    return kNumBuckets - 1 - b;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Counters reset (a kernel, so that it can sit inside a captured graph).
+// ---------------------------------------------------------------------------
+__global__ void reset_kernel(uint32_t *ctr, uint32_t *hist, const uint32_t *n_src, uint32_t n_imm)
+{
+    const int t = threadIdx.x;
+    if (t < CtrLayout::kN) ctr[t] = 0;
+    if (t == 0) ctr[CtrLayout::kN] = n_src ? *n_src : n_imm;
+    for (int i = t; i < kNumClasses * kNumBuckets; i += blockDim.x) hist[i] = 0;
+}
+
+__global__ void accum_errors_kernel(const uint32_t *ctr, uint32_t *acc)
+{
+    if (threadIdx.x == 0) acc[0] += ctr[CtrLayout::kErrors];
+}
+
+// ---------------------------------------------------------------------------
+// Record ingest: validation, seed score, class of both extensions.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) prep_kernel(BatchDev b, StoreDev st, Tuning tu, int stage)
+{
+    const uint32_t n = b.ctr[CtrLayout::kN];
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = r < n;
+    xdrop_record R{};
+    bool ok = false;
+    if (in) {
+        R = b.recs[r];
+        ok = record_ok(R, st);
+        b.valid[r] = ok ? 1 : 0;
+        if (!ok) atomicAdd(&b.ctr[CtrLayout::kErrors], 1u);
+    }
+    int cls = -1;
+    uint32_t key0 = 0, key1 = 0;
+    if (ok) {
+        const ReadInfo A = st.reads[R.read_a], B = st.reads[R.read_b];
+        const uint32_t pb = R.strand ? B.len - R.pos_b - R.k : R.pos_b;
+        const uint64_t bseed = R.strand ? B.rc + pb : B.fwd + pb;
+        int s = 0;
+        for (uint32_t t = 0; t < R.k; ++t)
+            s += code_at(st.words, A.fwd + R.pos_a + t) == code_at(st.words, bseed + t) ? R.match : R.mismatch;
+        b.seed[r] = s;
+        cls = kGenericClass;
+        for (int q = kWindowClasses - 1; q >= 0; --q)
+            if (R.x <= tu.x_class_limit[q]) cls = q;
+        key0 = min(R.pos_a, pb);
+        key1 = min(A.len - R.pos_a - R.k, B.len - pb - R.k);
+    }
+    // wave-aggregated queue appends (two tasks per record, same class)
+    uint32_t *dst = stage ? b.qkey : b.qbuf;
+    const uint32_t qcap = 2u * b.cap;
+    for (int q = 0; q < kNumClasses; ++q) {
+        const uint64_t mask = ballot(cls == q);
+        if (!mask) continue;
+        const int lane = lane_id();
+        const uint32_t cnt = 2u * (uint32_t)__builtin_popcountll(mask);
+        const uint32_t base = wave_fetch_add(&b.ctr[(stage ? CtrLayout::kStage : CtrLayout::kCount) + q], cnt);
+        if (cls == q) {
+            const uint32_t before = 2u * (uint32_t)__builtin_popcountll(mask & ((1ull << lane) - 1ull));
+            dst[q * qcap + base + before] = 2u * r;
+            dst[q * qcap + base + before + 1] = 2u * r + 1u;
+            if (stage) {
+                atomicAdd(&b.bucket_hist[q * kNumBuckets + bucket_of(key0)], 1u);
+                atomicAdd(&b.bucket_hist[q * kNumBuckets + bucket_of(key1)], 1u);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Length bucketing: counting sort of each class queue by quarter-octave
+// buckets of min(remaining A, remaining B), longest first.
+// ---------------------------------------------------------------------------
+__global__ void bucket_scan_kernel(BatchDev b)
+{
+    // one thread per class: exclusive scan of its histogram, counts copied
+    const int q = threadIdx.x;
+    if (q >= kNumClasses) return;
+    uint32_t acc = 0;
+    for (int k = 0; k < kNumBuckets; ++k) {
+        const uint32_t c = b.bucket_hist[q * kNumBuckets + k];
+        b.bucket_hist[q * kNumBuckets + k] = acc;
+        acc += c;
+    }
+    b.ctr[CtrLayout::kCount + q] = acc;
+}
+
+__global__ void __launch_bounds__(256) bucket_scatter_kernel(BatchDev b, StoreDev st)
+{
+    const uint32_t qcap = 2u * b.cap;
+    const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int q = 0; q < kNumClasses; ++q) {
+        const uint32_t cnt = b.ctr[CtrLayout::kStage + q];
+        if (idx >= cnt) continue;
+        const uint32_t t = b.qkey[q * qcap + idx];
+        const xdrop_record R = b.recs[t >> 1];
+        const ReadInfo A = st.reads[R.read_a], B = st.reads[R.read_b];
+        const uint32_t pb = R.strand ? B.len - R.pos_b - R.k : R.pos_b;
+        const uint32_t key = (t & 1) ? min(A.len - R.pos_a - R.k, B.len - pb - R.k) : min(R.pos_a, pb);
+        const uint32_t pos = atomicAdd(&b.bucket_hist[q * kNumBuckets + bucket_of(key)], 1u);
+        b.qbuf[q * qcap + pos] = t;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Register-window X-drop extension.
+// ---------------------------------------------------------------------------
+template <int C, bool COUNT>
+struct Window {
+    static constexpr int WIN = 64 * C;
+
+    int Z1[C];                // anti-diagonal d-1 (Z units)
+    int Z2[C];                // anti-diagonal d-2
+    uint32_t mmo[C], mme[C];  // mismatch bit (bit 2u) of pair u, odd / even anti-diagonal
+
+    // wave-uniform state
+    int base;                 // o_d = base + floor(d/2): i of slot 0 on anti-diagonal d
+    int T, bi, bj;
+    uint64_t cells;
+
+    // One anti-diagonal d (ODD = d & 1).  thr_p / thr_i: drop and improvement
+    // thresholds of d in Z units (T_{d-1} - X and T_{d-1}, plus |gap| * d).
+    template <bool ODD, bool BOUNDS>
+    __device__ __forceinline__ void step(int d, uint32_t ubit, int thr_p, int thr_i, int sm, int diff, int ma,
+                                         int G, int m, int n)
+    {
+        const int lane = lane_id();
+        int t[C];
+        if (ODD) {
+            // gap predecessors: slots s-1 and s of d-1 (wave_shr: lane l reads lane l-1)
+            t[0] = max(__builtin_amdgcn_update_dpp((int)0x80000000, Z1[C - 1], 0x138, 0xf, 0xf, false), Z1[0]);
+#pragma unroll
+            for (int r = 1; r < C; ++r) t[r] = max(Z1[r - 1], Z1[r]);
+        } else {
+            // gap predecessors: slots s and s+1 of d-1 (wave_shl: lane l reads lane l+1)
+#pragma unroll
+            for (int r = 0; r < C - 1; ++r) t[r] = max(Z1[r], Z1[r + 1]);
+            t[C - 1] = max(__builtin_amdgcn_update_dpp((int)0x80000000, Z1[0], 0x130, 0xf, 0xf, false), Z1[C - 1]);
+        }
+        int lo_s = 0, hi_s = 0;
+        if (BOUNDS) {
+            const int o = base + (d >> 1);
+            lo_s = max(0, d - n) - o;
+            hi_s = min(m, d) - o;
+        }
+        uint64_t imp = 0;
+        int v[C];
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            const uint32_t mm = ODD ? mmo[r] : mme[r];
+            const int bit = (int)__builtin_amdgcn_ubfe(mm, ubit, 1u);
+            v[r] = max(t[r], (Z2[r] + sm) - bit * diff);
+            const int s = C * lane + r;
+            const bool inb = !BOUNDS || (s >= lo_s && s <= hi_s);
+            imp |= ballot(inb && v[r] > thr_i);
+            if (COUNT) cells += (uint64_t)__builtin_popcountll(ballot(inb && v[r] > NEG_HALF));
+            t[r] = (inb && v[r] >= thr_p) ? v[r] : NEG;
+        }
+        if (imp) {
+            int vmax = thr_i + 1;
+            if (ma != 1) {
+                int lm = NEG;
+#pragma unroll
+                for (int r = 0; r < C; ++r) {
+                    const int s = C * lane + r;
+                    const bool inb = !BOUNDS || (s >= lo_s && s <= hi_s);
+                    lm = max(lm, inb ? v[r] : NEG);
+                }
+                vmax = uni(wave_max(lm));
+            }
+            // first slot (smallest lane, then smallest r) holding vmax
+            int rl = C;
+#pragma unroll
+            for (int r = C - 1; r >= 0; --r) {
+                const int s = C * lane + r;
+                const bool inb = !BOUNDS || (s >= lo_s && s <= hi_s);
+                if (inb && v[r] == vmax) rl = r;
+            }
+            const uint64_t any = ballot(rl < C);
+            const int l = __builtin_ctzll(any);
+            const int rr = __builtin_amdgcn_readlane(rl, l);
+            T = vmax - G * d;
+            bi = base + (d >> 1) + C * l + rr;
+            bj = d - bi;
+        }
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            Z2[r] = Z1[r];
+            Z1[r] = t[r];
+        }
+    }
+
+    // live slots over the last two anti-diagonals; false when both are dead
+    __device__ __forceinline__ bool band(int &mn, int &mx) const
+    {
+        mn = 1 << 30;
+        mx = -1;
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            const uint64_t u = ballot(max(Z1[r], Z2[r]) > NEG_HALF);
+            if (u) {
+                mn = min(mn, C * __builtin_ctzll(u) + r);
+                mx = max(mx, C * (63 - __builtin_clzll(u)) + r);
+            }
+        }
+        return mx >= 0;
+    }
+
+    // shift the window by delta slots: new slot s holds old slot s + delta
+    __device__ void recenter(int delta, int *lds)
+    {
+        const int lane = lane_id();
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            lds[C * lane + r] = Z1[r];
+            lds[WIN + C * lane + r] = Z2[r];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            const int s = C * lane + r + delta;
+            const bool ok = s >= 0 && s < WIN;
+            const int sc = ok ? s : 0;
+            const int a = lds[sc], b2 = lds[WIN + sc];
+            Z1[r] = ok ? a : NEG;
+            Z2[r] = ok ? b2 : NEG;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        base += delta;
+    }
+
+    // Run one extension.  Returns kStatusDone or kStatusOverflow.
+    __device__ uint32_t run(const uint32_t *__restrict__ W, int64_t maxp, const Geo &g, int X, int ma, int mi,
+                            int gap, int *lds)
+    {
+        const int lane = lane_id();
+        const int m = g.m, n = g.n;
+        const int G = -gap;
+        const int sm = ma + 2 * G;          // sigma(match) - 2*gap
+        const int diff = ma - mi;           // match - mismatch
+        const int s0 = WIN / 2 - 1;
+        base = -s0;                         // cell (0,0) in slot s0
+        T = 0; bi = 0; bj = 0; cells = 0;
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            Z1[r] = (C * lane + r == s0) ? 0 : NEG;
+            Z2[r] = NEG;
+        }
+        const int dend = m + n;
+        int d = 1;
+        while (d <= dend) {
+            int mn, mx;
+            if (!band(mn, mx)) break;                 // two dead anti-diagonals
+            const int width = mx - mn + 1;
+            if (width + 2 > WIN) return kStatusOverflow;
+            int U = min(UMAX, (WIN - width) / 2);
+            U = min(U, (dend - d + 2) >> 1);
+            if (mn < U || mx > WIN - 1 - U) recenter(mn - (WIN - width) / 2, lds);
+            // codes for this block: a from A0 + C*lane, b from B0 - C*lane - (C-1)
+            const int e0 = (d - 1) >> 1;
+            const int64_t A0 = (int64_t)base + e0 - 1;
+            const int64_t B0 = (int64_t)e0 - base;
+            const uint64_t aw = load32(W, (int64_t)g.abase + A0 + C * lane, maxp);
+            const uint64_t bw = load32(W, (int64_t)g.bbase + B0 - C * lane - (C - 1), maxp);
+#pragma unroll
+            for (int r = 0; r < C; ++r) {
+                const uint32_t bb = (uint32_t)(bw >> (2 * (C - 1 - r)));
+                const uint32_t xo = (uint32_t)(aw >> (2 * r)) ^ bb;
+                const uint32_t xe = (uint32_t)(aw >> (2 * (r + 1))) ^ bb;
+                mmo[r] = (xo | (xo >> 1)) & 0x55555555u;
+                mme[r] = (xe | (xe >> 1)) & 0x55555555u;
+            }
+            const int dlast = d + 2 * U - 1;
+            const int o_first = base + (d >> 1), o_last = base + (dlast >> 1);
+            const bool fast = o_first >= 0 && o_last >= dlast - n && o_last + WIN - 1 <= m &&
+                              o_first + WIN - 1 <= d;
+            if (fast) {
+                for (int u = 0; u < U; ++u) {
+                    const int dd = d + 2 * u;
+                    const uint32_t ub = 2u * (uint32_t)u;
+                    step<true, false>(dd, ub, T - X + G * dd, T + G * dd, sm, diff, ma, G, m, n);
+                    step<false, false>(dd + 1, ub, T - X + G * (dd + 1), T + G * (dd + 1), sm, diff, ma, G, m, n);
+                }
+            } else {
+                for (int u = 0; u < U; ++u) {
+                    const int dd = d + 2 * u;
+                    const uint32_t ub = 2u * (uint32_t)u;
+                    step<true, true>(dd, ub, T - X + G * dd, T + G * dd, sm, diff, ma, G, m, n);
+                    step<false, true>(dd + 1, ub, T - X + G * (dd + 1), T + G * (dd + 1), sm, diff, ma, G, m, n);
+                }
+            }
+            d += 2 * U;
+        }
+        return kStatusDone;
+    }
+};
+
+template <int C, bool COUNT>
+__global__ void __launch_bounds__(256) window_kernel(BatchDev b, StoreDev st, int cls)
+{
+    extern __shared__ int lds_all[];
+    const int wave = threadIdx.x >> 6;
+    int *lds = lds_all + wave * (2 * 64 * C);
+    const uint32_t qcap = 2u * b.cap;
+    const uint32_t cnt = b.ctr[CtrLayout::kCount + cls];
+    Window<C, COUNT> w;
+    for (;;) {
+        const uint32_t idx = wave_fetch_add(&b.ctr[CtrLayout::kHead + cls], 1u);
+        if (idx >= cnt) break;
+        const uint32_t t = (uint32_t)uni((int)b.qbuf[cls * qcap + idx]);
+        const Task k = load_task(b.recs, st.reads, t);
+        const uint32_t status = w.run(st.words, st.max_base, k.g, k.x, k.ma, k.mi, k.gap, lds);
+        if (status == kStatusDone) {
+            // every lane stores the same (wave-uniform) values
+            TaskOut o;
+            o.score = w.T; o.i = w.bi; o.j = w.bj; o.status = kStatusDone; o.cells = w.cells;
+            b.tout[t] = o;
+        } else {
+            const uint32_t pos = wave_fetch_add(&b.ctr[CtrLayout::kCount + cls + 1], 1u);
+            b.qbuf[(cls + 1) * qcap + pos] = t;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Unbounded X-drop extension: three anti-diagonals in global memory, indexed
+// by i, with the live range [lo, hi] of each; one wavefront sweeps the
+// candidate range of each anti-diagonal 64 cells at a time.
+// ---------------------------------------------------------------------------
+template <bool COUNT>
+__device__ void generic_run(const uint32_t *__restrict__ W, const Geo &g, int X, int ma, int mi, int gap,
+                            int *P2, int *P1, int *P0, int dummy, TaskOut &o)
+{
+    const int lane = lane_id();
+    const int m = g.m, n = g.n;
+    int lo2 = 1, hi2 = 0, lo1 = 0, hi1 = 0;
+    P1[0] = 0;   // every lane writes the same value
+    __threadfence_block();
+    int T = 0, bi = 0, bj = 0;
+    uint64_t cells = 0;
+    bool prev_dead = false;
+    for (int d = 1; d <= m + n; ++d) {
+        const int ilo = max(0, d - n), ihi = min(m, d);
+        int slo = 1 << 30, shi = -(1 << 30);
+        if (lo1 <= hi1) { slo = min(slo, lo1); shi = max(shi, hi1 + 1); }
+        if (lo2 <= hi2) { slo = min(slo, lo2 + 1); shi = max(shi, hi2 + 1); }
+        slo = max(slo, ilo);
+        shi = min(shi, ihi);
+        int nlo = 1 << 30, nhi = -1, dmax = NEG, dmi = -1;
+        const int thr = T - X;
+        for (int i0 = slo; i0 <= shi; i0 += 64) {
+            const int i = i0 + lane;
+            const bool act = i <= shi;
+            const int j = d - i;
+            // branch-free: every lane loads from clamped (always valid) indices
+            const int im1 = min(max(i - 1, 0), dummy), ic = min(max(i, 0), dummy);
+            const bool hd = act && i >= 1 && j >= 1 && i - 1 >= lo2 && i - 1 <= hi2;
+            const bool hu = act && i >= 1 && i - 1 >= lo1 && i - 1 <= hi1;
+            const bool hl = act && j >= 1 && i >= lo1 && i <= hi1;
+            const int pd = P2[im1], pu = P1[im1], pl = P1[ic];
+            const int ia = min(max(i - 1, 0), max(m - 1, 0)), jb = min(max(j - 1, 0), max(n - 1, 0));
+            const uint32_t ca = code_at(W, g.abase + (uint64_t)ia);
+            const uint32_t cb = code_at(W, g.bbase + (uint64_t)jb);
+            const bool okd = hd && pd > NEG_HALF, oku = hu && pu > NEG_HALF, okl = hl && pl > NEG_HALF;
+            int v = NEG;
+            v = max(v, okd ? pd + (ca == cb ? ma : mi) : NEG);
+            v = max(v, oku ? pu + gap : NEG);
+            v = max(v, okl ? pl + gap : NEG);
+            const bool cand = okd || oku || okl;
+            const bool lv = cand && v >= thr;
+            // lanes past the range write an index that is never read (no divergent branch)
+            P0[act ? i : dummy] = lv ? v : NEG;
+            if (COUNT) cells += (uint64_t)__builtin_popcountll(ballot(cand));
+            const uint64_t lmask = ballot(lv);
+            if (lmask) {
+                if (nhi < 0) nlo = i0 + __builtin_ctzll(lmask);
+                nhi = i0 + 63 - __builtin_clzll(lmask);
+                const int cmax = uni(wave_max(lv ? v : NEG));
+                if (cmax > dmax) {
+                    const uint64_t e = ballot(lv && v == cmax);
+                    dmax = cmax;
+                    dmi = i0 + __builtin_ctzll(e);
+                }
+            }
+        }
+        __threadfence_block();
+        const bool live = nhi >= 0;
+        if (live && dmax > T) { T = dmax; bi = dmi; bj = d - dmi; }
+        int *tp = P2; P2 = P1; P1 = P0; P0 = tp;
+        lo2 = lo1; hi2 = hi1;
+        lo1 = live ? nlo : 1; hi1 = live ? nhi : 0;
+        if (!live && prev_dead) break;
+        prev_dead = !live;
+    }
+    o.score = T; o.i = bi; o.j = bj; o.status = kStatusDone; o.cells = cells;
+}
+
+template <bool COUNT>
+__global__ void __launch_bounds__(256) generic_kernel(BatchDev b, StoreDev st, int32_t *scratch, uint64_t stride)
+{
+    const uint32_t qcap = 2u * b.cap;
+    const int cls = kGenericClass;
+    const uint32_t cnt = b.ctr[CtrLayout::kCount + cls];
+    const uint64_t wave_global = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    int *base = scratch + wave_global * 3 * stride;
+    for (;;) {
+        const uint32_t idx = wave_fetch_add(&b.ctr[CtrLayout::kHead + cls], 1u);
+        if (idx >= cnt) break;
+        const uint32_t t = (uint32_t)uni((int)b.qbuf[cls * qcap + idx]);
+        const Task k = load_task(b.recs, st.reads, t);
+        TaskOut o;
+        generic_run<COUNT>(st.words, k.g, k.x, k.ma, k.mi, k.gap, base, base + stride, base + 2 * stride,
+                           (int)stride - 1, o);
+        b.tout[t] = o;   // same values in every lane
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Result write-back.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) finalize_kernel(BatchDev b, StoreDev st)
+{
+    const uint32_t n = b.ctr[CtrLayout::kN];
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    xdrop_result out{};
+    uint64_t c = 0;
+    if (b.valid[r]) {
+        const xdrop_record R = b.recs[r];
+        const ReadInfo B = st.reads[R.read_b];
+        const uint32_t pb = R.strand ? B.len - R.pos_b - R.k : R.pos_b;
+        const TaskOut L = b.tout[2 * r], Rt = b.tout[2 * r + 1];
+        const int s = b.seed[r];
+        out.left_score = L.score;
+        out.right_score = Rt.score;
+        out.seed_score = s;
+        out.score = L.score + s + Rt.score;
+        out.a_begin = R.pos_a - (uint32_t)L.i;
+        out.a_end = R.pos_a + R.k + (uint32_t)Rt.i;
+        out.b_begin = pb - (uint32_t)L.j;
+        out.b_end = pb + R.k + (uint32_t)Rt.j;
+        c = L.cells + Rt.cells;
+    }
+    b.res[r] = out;
+    if (b.cells) b.cells[r] = c;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+void launch_reset_n(const BatchDev &b, const uint32_t *n_src, uint32_t n_imm, hipStream_t s)
+{
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, s, b.ctr, b.bucket_hist, n_src, n_imm);
+}
+
+void launch_accum_errors(const BatchDev &b, uint32_t *acc, hipStream_t s)
+{
+    hipLaunchKernelGGL(accum_errors_kernel, dim3(1), dim3(64), 0, s, (const uint32_t *)b.ctr, acc);
+}
+
+void launch_prep(const BatchDev &b, const StoreDev &st, const Tuning &tu, uint32_t n, bool stage, hipStream_t s)
+{
+    const uint32_t blocks = (n + 255) / 256;
+    if (blocks) hipLaunchKernelGGL(prep_kernel, dim3(blocks), dim3(256), 0, s, b, st, tu, stage ? 1 : 0);
+}
+
+void launch_bucket(const BatchDev &b, const StoreDev &st, uint32_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(64), 0, s, b);
+    const uint32_t blocks = (2 * n + 255) / 256;
+    if (blocks) hipLaunchKernelGGL(bucket_scatter_kernel, dim3(blocks), dim3(256), 0, s, b, st);
+}
+
+template <int C>
+static void launch_window_c(const BatchDev &b, const StoreDev &st, int cls, uint32_t grid_waves, bool count,
+                            hipStream_t s)
+{
+    const uint32_t blocks = (grid_waves + 3) / 4;
+    const size_t lds = 4 * 2 * 64 * C * sizeof(int);
+    if (count)
+        hipLaunchKernelGGL((window_kernel<C, true>), dim3(blocks), dim3(256), lds, s, b, st, cls);
+    else
+        hipLaunchKernelGGL((window_kernel<C, false>), dim3(blocks), dim3(256), lds, s, b, st, cls);
+}
+
+void launch_window(int cls, const BatchDev &b, const StoreDev &st, uint32_t grid_waves, bool count_cells,
+                   hipStream_t s)
+{
+    switch (kWindowC[cls]) {
+    case 1: launch_window_c<1>(b, st, cls, grid_waves, count_cells, s); break;
+    case 2: launch_window_c<2>(b, st, cls, grid_waves, count_cells, s); break;
+    case 3: launch_window_c<3>(b, st, cls, grid_waves, count_cells, s); break;
+    case 4: launch_window_c<4>(b, st, cls, grid_waves, count_cells, s); break;
+    case 16: launch_window_c<16>(b, st, cls, grid_waves, count_cells, s); break;
+    default: break;
+    }
+}
+
+void launch_generic(const BatchDev &b, const StoreDev &st, int32_t *scratch, uint64_t stride, uint32_t grid_waves,
+                    bool count_cells, hipStream_t s)
+{
+    const uint32_t blocks = grid_waves / 4;   // scratch holds exactly grid_waves (a multiple of 4) wavefronts
+    if (count_cells)
+        hipLaunchKernelGGL(generic_kernel<true>, dim3(blocks), dim3(256), 0, s, b, st, scratch, stride);
+    else
+        hipLaunchKernelGGL(generic_kernel<false>, dim3(blocks), dim3(256), 0, s, b, st, scratch, stride);
+}
+
+void launch_finalize(const BatchDev &b, const StoreDev &st, uint32_t n, hipStream_t s)
+{
+    const uint32_t blocks = (n + 255) / 256;
+    if (blocks) hipLaunchKernelGGL(finalize_kernel, dim3(blocks), dim3(256), 0, s, b, st);
+}
+
+}  // namespace xd

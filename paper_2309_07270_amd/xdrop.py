@@ -1,0 +1,179 @@
+"""Thin ctypes binding of libxdrop.so (include/xdrop.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  If the library has not been built the import of a
+binding function raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .workload import RECORD_DTYPE, RESULT_DTYPE, ReadStore, ASCII
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libxdrop.so")
+
+XDROP_OK = 0
+XDROP_E_INVALID = -1
+XDROP_E_NOMEM = -2
+XDROP_E_DEVICE = -3
+XDROP_E_TIMEOUT = -4
+XDROP_E_BUSY = -5
+XDROP_E_STATE = -6
+MODE_PERSISTENT = 0
+MODE_PLAIN = 1
+MAX_X = 1 << 30
+
+EXPORTED = ("xdrop_batch_create", "xdrop_batch_submit", "xdrop_batch_submit_device", "xdrop_batch_wait",
+            "xdrop_batch_destroy", "xdrop_status_string", "xdrop_last_error")
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("reads", ctypes.POINTER(ctypes.c_char_p)), ("lengths", ctypes.POINTER(ctypes.c_uint32)),
+                ("n_reads", ctypes.c_uint32), ("device", ctypes.c_int32), ("mode", ctypes.c_uint32),
+                ("max_inflight", ctypes.c_uint32), ("hbm_budget_bytes", ctypes.c_uint64),
+                ("tuning_cache", ctypes.c_char_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("records", ctypes.c_uint64), ("cells", ctypes.c_uint64), ("queue_ms", ctypes.c_double),
+                ("device_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class XdropError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"xdrop status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libxdrop.so; raises if it is missing (build it with __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libxdrop.so not built at {path}; run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    lib.xdrop_batch_create.argtypes = [P(Config), P(vp)]
+    lib.xdrop_batch_submit.argtypes = [vp, vp, ctypes.c_size_t, vp, vp, ctypes.c_int64, P(ctypes.c_uint64)]
+    lib.xdrop_batch_submit_device.argtypes = [vp, vp, ctypes.c_size_t, vp, vp, vp, P(ctypes.c_uint64)]
+    lib.xdrop_batch_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_int64, P(Stats)]
+    lib.xdrop_batch_destroy.argtypes = [vp]
+    lib.xdrop_status_string.argtypes = [ctypes.c_int]
+    lib.xdrop_status_string.restype = ctypes.c_char_p
+    lib.xdrop_last_error.argtypes = [vp]
+    lib.xdrop_last_error.restype = ctypes.c_char_p
+    for f in ("xdrop_batch_create", "xdrop_batch_submit", "xdrop_batch_submit_device", "xdrop_batch_wait",
+              "xdrop_batch_destroy"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a) -> int:
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return int(a.data_ptr())  # torch tensor
+
+
+class Context:
+    """One xdrop context: a device-resident read store plus batch execution."""
+
+    def __init__(self, reads, device: int = 0, mode: int = MODE_PERSISTENT, max_inflight: int = 4,
+                 hbm_budget_bytes: int = 0, tuning_cache: str | None = None):
+        self.lib = load_library()
+        if isinstance(reads, ReadStore):
+            seqs = [ASCII[reads.read(r)].tobytes() for r in range(reads.n)]
+        else:
+            seqs = [s.encode() if isinstance(s, str) else bytes(s) for s in reads]
+        self._seqs = seqs
+        arr = (ctypes.c_char_p * len(seqs))(*seqs)
+        lens = (ctypes.c_uint32 * len(seqs))(*[len(s) for s in seqs])
+        cfg = Config(arr, lens, len(seqs), device, mode, max_inflight, hbm_budget_bytes,
+                     tuning_cache.encode() if tuning_cache else None)
+        h = ctypes.c_void_p()
+        st = self.lib.xdrop_batch_create(ctypes.byref(cfg), ctypes.byref(h))
+        self._seqs = None
+        if st != XDROP_OK:
+            raise XdropError(st, self.lib.xdrop_last_error(None).decode())
+        self.h = h
+        self.n_reads = len(seqs)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.xdrop_batch_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def error(self) -> str:
+        return self.lib.xdrop_last_error(self.h).decode()
+
+    def _check(self, st):
+        if st != XDROP_OK:
+            raise XdropError(st, self.error() or self.lib.xdrop_status_string(st).decode())
+
+    # -- host path ---------------------------------------------------------
+    def submit(self, recs: np.ndarray, out: np.ndarray | None = None, cells: np.ndarray | None = None,
+               count_cells: bool = False, admit_timeout_us: int = -1):
+        recs = np.ascontiguousarray(recs, dtype=RECORD_DTYPE)
+        n = recs.size
+        if out is None:
+            out = np.zeros(n, RESULT_DTYPE)
+        if cells is None and count_cells:
+            cells = np.zeros(n, np.uint64)
+        t = ctypes.c_uint64()
+        st = self.lib.xdrop_batch_submit(self.h, _ptr(recs) if n else None, n, _ptr(out) if n else None,
+                                         _ptr(cells) if (cells is not None and n) else None,
+                                         admit_timeout_us, ctypes.byref(t))
+        self._check(st)
+        return t.value, out, cells
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> dict:
+        s = Stats()
+        st = self.lib.xdrop_batch_wait(self.h, ticket, timeout_us, ctypes.byref(s))
+        self._check(st)
+        return s.as_dict()
+
+    def run(self, recs: np.ndarray, count_cells: bool = False):
+        """Submit one host batch and wait: (results, cells or None, stats)."""
+        t, out, cells = self.submit(recs, count_cells=count_cells)
+        stats = self.wait(t)
+        return out, cells, stats
+
+    # -- device path (torch tensors or raw device pointers) ----------------
+    def submit_device(self, d_recs, n: int, d_out, d_cells=None, stream=None) -> int:
+        t = ctypes.c_uint64()
+        sp = None if stream is None else int(getattr(stream, "cuda_stream", stream))
+        st = self.lib.xdrop_batch_submit_device(self.h, _ptr(d_recs), n, _ptr(d_out),
+                                                _ptr(d_cells) if d_cells is not None else None, sp,
+                                                ctypes.byref(t))
+        self._check(st)
+        return t.value
+
+
+def status_string(st: int) -> str:
+    return load_library().xdrop_status_string(st).decode()

@@ -1,0 +1,163 @@
+"""GPU parity: libxdrop.so (through its C ABI) against the CPU oracle, bit-exact.
+
+Every compared field is an integer, so the bar is equality: scores, the four
+span coordinates and the per-record cell counts.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_07270_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = (("score", "score"), ("left_score", "left"), ("right_score", "right"), ("seed_score", "seed"),
+          ("a_begin", "a_begin"), ("a_end", "a_end"), ("b_begin", "b_begin"), ("b_end", "b_end"))
+
+
+def note(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def assert_same(res, cells, ref, idx=None):
+    idx = np.arange(len(res)) if idx is None else idx
+    for fg, fr in FIELDS:
+        g = res[fg].astype(np.int64)
+        r = ref[fr].astype(np.int64)
+        if not np.array_equal(g, r):
+            bad = np.flatnonzero(g != r)
+            raise AssertionError(f"{fg}: {bad.size} records differ, first record {int(idx[bad[0]])}: "
+                                 f"gpu {int(g[bad[0]])} oracle {int(r[bad[0]])}")
+    if cells is not None:
+        want = (ref["cells_left"] + ref["cells_right"]).astype(np.uint64)
+        if not np.array_equal(cells.astype(np.uint64), want):
+            bad = np.flatnonzero(cells.astype(np.uint64) != want)
+            raise AssertionError(f"cells: {bad.size} records differ, first {int(idx[bad[0]])}: "
+                                 f"gpu {int(cells[bad[0]])} oracle {int(want[bad[0]])}")
+
+
+@pytest.fixture(scope="module")
+def xd():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2309_07270_amd import xdrop
+    xdrop.load_library()
+    return xdrop
+
+
+@pytest.fixture(scope="module")
+def c0():
+    wl = W.make_workload("c0")
+    ref, _ = oracle.batch(wl.store.codes, wl.store.off, wl.store.length, wl.records)
+    return wl, ref
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_c0_bit_exact(xd, c0, mode):
+    wl, ref = c0
+    note(f"c0 1000 records mode={mode}")
+    with xd.Context(wl.store, mode=mode) as ctx:
+        res, cells, st = ctx.run(wl.records, count_cells=True)
+        res2, cells2, _ = ctx.run(wl.records, count_cells=False)
+    assert_same(res, cells, ref)
+    assert_same(res2, None, ref)
+    assert st["cells"] == int(cells.sum())
+
+
+def small_case(seed, n_reads, lo, hi, n_recs, x_choices):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    store = W.random_store(rng, n_reads, lo, hi)
+    recs = W.random_records(rng, store, n_recs, x_choices=x_choices)
+    ref, _ = oracle.batch(store.codes, store.off, store.length, recs)
+    return store, recs, ref
+
+
+@pytest.mark.parametrize("seed,lo,hi,xs", [
+    (11, 1, 40, (0, 1, 2, 3, 5)),
+    (12, 20, 400, (0, 5, 20, 50)),
+    (13, 300, 1500, (10, 50, 100)),
+])
+def test_random_records_bit_exact(xd, seed, lo, hi, xs):
+    store, recs, ref = small_case(seed, 60, lo, hi, 3000, xs)
+    note(f"random records seed={seed} len=[{lo},{hi}] X={xs}")
+    for mode in (0, 1):
+        with xd.Context(store, mode=mode) as ctx:
+            res, cells, _ = ctx.run(recs, count_cells=True)
+        assert_same(res, cells, ref)
+
+
+def test_wide_bands_escalate(xd):
+    # X = 2^30 never drops a cell: the band grows to the whole table and the
+    # task has to climb through every window class into the unbounded kernel.
+    rng = np.random.Generator(np.random.PCG64(21))
+    store = W.random_store(rng, 12, 200, 2600, related=0.8)
+    recs = W.random_records(rng, store, 40, x_choices=(W_INF := 1 << 30, 300, 1000), k_max=5)
+    ref, _ = oracle.batch(store.codes, store.off, store.length, recs)
+    note("wide bands: X up to 2^30, reads up to 2.6 kb")
+    with xd.Context(store) as ctx:
+        res, cells, _ = ctx.run(recs, count_cells=True)
+    assert_same(res, cells, ref)
+
+
+def test_identical_reads_full_length(xd):
+    rng = np.random.Generator(np.random.PCG64(5))
+    seq = rng.integers(0, 4, 3000).astype(np.uint8)
+    store = W.ReadStore(np.concatenate([seq, seq]), np.array([0, 3000]), np.array([3000, 3000]))
+    recs = np.zeros(6, W.RECORD_DTYPE)
+    recs["read_a"], recs["read_b"] = 0, 1
+    recs["pos_a"] = recs["pos_b"] = [0, 1000, 2983, 5, 1500, 0]
+    recs["k"] = 17
+    recs["x"] = [0, 1, 20, 50, 100, 1 << 30]
+    recs["match"], recs["mismatch"], recs["gap"] = 1, -1, -1
+    note("identical reads")
+    with xd.Context(store) as ctx:
+        res, cells, _ = ctx.run(recs, count_cells=True)
+    assert np.all(res["score"] == 3000)
+    assert np.all(res["a_begin"] == 0) and np.all(res["a_end"] == 3000)
+    ref, _ = oracle.batch(store.codes, store.off, store.length, recs)
+    assert_same(res, cells, ref)
+
+
+def test_device_path(xd, c0):
+    import torch
+    wl, ref = c0
+    note("device path (torch tensors)")
+    d_recs = torch.from_numpy(wl.records.view(np.uint8)).cuda()
+    d_out = torch.zeros(len(wl.records) * 32, dtype=torch.uint8, device="cuda")
+    d_cells = torch.zeros(len(wl.records), dtype=torch.int64, device="cuda")
+    with xd.Context(wl.store) as ctx:
+        stream = torch.cuda.current_stream()
+        t = ctx.submit_device(d_recs, len(wl.records), d_out, d_cells, stream=stream)
+        ctx.wait(t)
+        torch.cuda.synchronize()
+    res = d_out.cpu().numpy().view(W.RESULT_DTYPE)
+    assert_same(res, d_cells.cpu().numpy().astype(np.uint64), ref)
+
+
+def test_invalid_and_empty(xd, c0):
+    wl, _ = c0
+    note("invalid records and empty batch")
+    with xd.Context(wl.store) as ctx:
+        out, _, st = ctx.run(wl.records[:0])
+        assert out.size == 0 and st["records"] == 0
+        for field, val in (("read_a", 10 ** 6), ("k", 0), ("x", -1), ("gap", 0), ("pos_a", 10 ** 6)):
+            bad = wl.records[:5].copy()
+            bad[field][2] = val
+            with pytest.raises(xd.XdropError) as e:
+                ctx.submit(bad)
+            assert e.value.status == xd.XDROP_E_INVALID
+        # the device path validates on the GPU: the ticket reports the error
+        import torch
+        bad = wl.records[:300].copy()
+        bad["read_b"][7] = 10 ** 7
+        d_recs = torch.from_numpy(bad.view(np.uint8)).cuda()
+        d_out = torch.zeros(300 * 32, dtype=torch.uint8, device="cuda")
+        t = ctx.submit_device(d_recs, 300, d_out)
+        with pytest.raises(xd.XdropError) as e:
+            ctx.wait(t)
+        assert e.value.status == xd.XDROP_E_INVALID
+        res, _, _ = ctx.run(wl.records[:10])
+        assert np.all(res["score"] > 0)
