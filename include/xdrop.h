@@ -26,8 +26,8 @@
  * are exact int32; nothing is approximated.  Reads are ASCII A/C/G/T (either
  * case).  Coordinates are 0-based, spans half-open.
  *
- * Threading: xdrop_batch_submit*, xdrop_batch_wait and xdrop_batch_query may
- * be called concurrently from many threads on one context (producers).
+ * Threading: xdrop_batch_submit*, xdrop_batch_wait may be called concurrently
+ * from many threads on one context (producers).
  * xdrop_batch_destroy must not race any other call on the same context.
  */
 #ifndef XDROP_H
@@ -70,7 +70,23 @@ typedef struct {
     uint32_t max_inflight;        /* batches admitted at once; 0 -> 4       */
     uint64_t hbm_budget_bytes;    /* device bytes for in-flight batches; 0 -> 8 GiB */
     const char *tuning_cache;     /* path of the autotuner cache, or NULL   */
+    uint32_t flags;               /* XDROP_FLAG_*                           */
 } xdrop_config;
+
+enum {
+    XDROP_FLAG_PROFILE = 1        /* time every kernel stage with HIP events
+                                     (stats.stage_ms); adds ~1 us per stage  */
+};
+
+/* Kernel stages reported in xdrop_batch_stats.stage_ms / stage_cells. */
+enum {
+    XDROP_STAGE_INGEST = 0,       /* counter reset, validation, seed, classes, bucketing */
+    XDROP_STAGE_WINDOW0 = 1,      /* register-window classes 0..4 (64, 128, 192, 256,
+                                     1024-cell windows)                      */
+    XDROP_STAGE_GENERIC = 6,      /* unbounded band kernel                  */
+    XDROP_STAGE_FINALIZE = 7,     /* result write-back                      */
+    XDROP_NUM_STAGES = 8
+};
 
 #define XDROP_MAX_READ_LEN (1u << 24)
 #define XDROP_MAX_X (1 << 30)
@@ -83,7 +99,9 @@ typedef struct {                  /* 32 bytes, little-endian, packed naturally *
     uint8_t pad;
     int32_t x;                    /* drop, 0 <= x <= XDROP_MAX_X            */
     int16_t match, mismatch, gap; /* match >= 1, mismatch < match, gap <= -1;
-                                     |weights| <= 1024                      */
+                                     |weights| <= 1024 and
+                                     (match - mismatch - gap) * (|A| + |B|) <= 2^29,
+                                     which keeps every score inside int32 */
     int16_t pad2;
 } xdrop_record;
 
@@ -103,6 +121,12 @@ typedef struct {
     double queue_ms;              /* submit entry -> admitted               */
     double device_ms;             /* first kernel start -> last kernel end  */
     double total_ms;              /* submit entry -> completion             */
+    double stage_ms[XDROP_NUM_STAGES];      /* XDROP_FLAG_PROFILE only; summed over
+                                               chunks in the plain form    */
+    uint64_t stage_cells[XDROP_NUM_STAGES]; /* cells of the extensions each stage
+                                               completed (cell counting, persistent
+                                               form only)                  */
+    uint64_t stage_tasks[XDROP_NUM_STAGES]; /* extensions each stage completed (idem) */
 } xdrop_batch_stats;
 
 /* Create a context on cfg->device: packs the reads to 2 bits per base (both

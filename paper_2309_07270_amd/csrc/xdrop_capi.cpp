@@ -90,6 +90,9 @@ struct Ticket {
     double t_submit = 0, t_admit = 0, t_done = 0;
     float dev_ms = 0.f;
     uint64_t total_cells = 0;
+    double stage_ms[XDROP_NUM_STAGES] = {};
+    uint64_t stage_cells[XDROP_NUM_STAGES] = {};
+    uint64_t stage_tasks[XDROP_NUM_STAGES] = {};
 };
 
 struct Slot {
@@ -107,6 +110,8 @@ struct Slot {
     uint32_t *h_misc = nullptr;       // [0] = n, [1] = error count
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+    std::vector<hipEvent_t> sev;      // stage boundary events, 9 per chunk (profiling)
+    unsigned long long *h_stage = nullptr;   // pinned copy of the per-stage sums
     hipGraphExec_t graph[2] = {nullptr, nullptr};   // [count_cells]
     bool busy = false;
     std::shared_ptr<Ticket> job;
@@ -123,6 +128,8 @@ struct xdrop_ctx {
     uint64_t budget = 8ull << 30;
     uint64_t used = 0;
     int cus = 256;
+    bool profile = false;
+    std::atomic<bool> use_graph{true};
 
     // store
     uint32_t *d_words = nullptr;
@@ -229,6 +236,7 @@ size_t slot_bytes(uint32_t cap)
     add((size_t)kNumClasses * 2 * n * sizeof(uint32_t));   // qkey
     add(CtrLayout::kWords * sizeof(uint32_t) + 64);
     add((size_t)kNumClasses * kNumBuckets * sizeof(uint32_t));
+    add(16 * sizeof(unsigned long long));
     return b;
 }
 
@@ -242,6 +250,10 @@ void free_slot_buffers(Slot &s)
     if (s.h_res) hipHostFree(s.h_res);
     if (s.h_cells) hipHostFree(s.h_cells);
     if (s.h_misc) hipHostFree(s.h_misc);
+    if (s.h_stage) hipHostFree(s.h_stage);
+    for (auto e : s.sev) hipEventDestroy(e);
+    s.sev.clear();
+    s.h_stage = nullptr;
     s.dblock = nullptr; s.scratch = nullptr; s.h_recs = nullptr; s.h_res = nullptr; s.h_cells = nullptr;
     s.h_misc = nullptr;
     s.cap = 0;
@@ -271,6 +283,7 @@ void alloc_slot_buffers(xdrop_ctx *c, Slot &s, uint32_t cap)
     s.dev.ctr = (uint32_t *)take(CtrLayout::kWords * sizeof(uint32_t) + 64);
     s.d_n = s.dev.ctr + CtrLayout::kWords;
     s.dev.bucket_hist = (uint32_t *)take((size_t)kNumClasses * kNumBuckets * sizeof(uint32_t));
+    s.dev.stage_sum = (unsigned long long *)take(16 * sizeof(unsigned long long));
     s.dev.cap = cap;
     // generic-kernel scratch: three anti-diagonals per wavefront
     s.generic_waves = (uint32_t)((std::max(4, c->tune.generic_waves) + 3) / 4 * 4);   // whole blocks of 4
@@ -281,6 +294,12 @@ void alloc_slot_buffers(xdrop_ctx *c, Slot &s, uint32_t cap)
     HIP_TRY(hipHostMalloc((void **)&s.h_res, n * sizeof(xdrop_result), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void **)&s.h_cells, n * sizeof(uint64_t), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void **)&s.h_misc, 64, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void **)&s.h_stage, 16 * sizeof(unsigned long long), hipHostMallocDefault));
+    if (c->profile) {
+        const size_t chunks = c->mode == XDROP_MODE_PLAIN ? (cap + kPlainChunk - 1) / kPlainChunk : 1;
+        s.sev.resize(9 * chunks, nullptr);
+        for (auto &e : s.sev) HIP_TRY(hipEventCreate(&e));
+    }
 }
 
 size_t slot_footprint(const xdrop_ctx *c, uint32_t cap)
@@ -299,31 +318,54 @@ uint32_t round_cap(size_t n)
 // Kernel sequence of one batch (or chunk) on `s`.  `b` may be a view into the
 // slot buffers (plain chunks); n_src non-null means "read n from device".
 void enqueue_kernels(xdrop_ctx *c, Slot &sl, const BatchDev &b, uint32_t n, const uint32_t *n_src, bool persistent,
-                     bool count, hipStream_t s)
+                     bool count, hipStream_t s, hipEvent_t *ev)
 {
+    // ev (nullable): 9 stage-boundary events recorded between the launches
+    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     launch_reset_n(b, n_src, n, s);
     const bool stage = persistent && c->tune.buckets > 0;
     launch_prep(b, c->st, c->tune, n, stage, s);
     if (stage) launch_bucket(b, c->st, n, s);
+    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     const uint32_t resident = (uint32_t)c->cus * (uint32_t)std::max(1, c->tune.waves_per_cu);
     for (int q = 0; q < kWindowClasses; ++q) {
         uint32_t waves = persistent ? resident : std::max<uint32_t>(2 * n, 4);
         launch_window(q, b, c->st, waves, count, s);
+        if (ev) HIP_TRY(hipEventRecord(ev[2 + q], s));
     }
     launch_generic(b, c->st, sl.scratch, sl.scratch_stride, sl.generic_waves, count, s);
-    launch_finalize(b, c->st, n, s);
+    if (ev) HIP_TRY(hipEventRecord(ev[7], s));
+    launch_finalize(b, c->st, n, count, s);
+    if (ev) HIP_TRY(hipEventRecord(ev[8], s));
 }
 
+// The persistent form's kernel sequence captured once per slot (and per cell
+// counting flag); kernels read the batch size from device memory, so one
+// graph serves every batch up to the slot capacity.  With profiling on, the
+// stage events are captured as event-record nodes; if the runtime refuses
+// that, profiling falls back to direct launches of the same kernels.
 hipGraphExec_t get_graph(xdrop_ctx *c, Slot &sl, bool count)
 {
     hipGraphExec_t &g = sl.graph[count ? 1 : 0];
     if (g) return g;
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal));
-    enqueue_kernels(c, sl, sl.dev, sl.cap, sl.d_n, true, count, sl.stream);
+    try {
+        enqueue_kernels(c, sl, sl.dev, sl.cap, sl.d_n, true, count, sl.stream,
+                        c->profile ? sl.sev.data() : nullptr);
+    } catch (...) {
+        hipStreamEndCapture(sl.stream, &graph);
+        if (graph) hipGraphDestroy(graph);
+        hipGetLastError();
+        throw;
+    }
     HIP_TRY(hipStreamEndCapture(sl.stream, &graph));
-    HIP_TRY(hipGraphInstantiate(&g, graph, nullptr, nullptr, 0));
+    const hipError_t e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
     hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        g = nullptr;
+        throw std::runtime_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
     return g;
 }
 
@@ -341,14 +383,27 @@ void run_batch(xdrop_ctx *c, Slot &sl, Ticket &t)
     HIP_TRY(hipMemcpyAsync(sl.d_n, sl.h_misc, sizeof(uint32_t), hipMemcpyHostToDevice, s));
     HIP_TRY(hipEventRecord(sl.ev0, s));
     if (c->mode == XDROP_MODE_PERSISTENT) {
-        HIP_TRY(hipGraphLaunch(get_graph(c, sl, count), s));
+        hipGraphExec_t g = nullptr;
+        if (c->use_graph) {
+            try {
+                g = get_graph(c, sl, count);
+            } catch (const std::exception &e) {
+                if (!c->profile) throw;
+                c->use_graph = false;   // profiling events could not be captured
+            }
+        }
+        if (g)
+            HIP_TRY(hipGraphLaunch(g, s));
+        else
+            enqueue_kernels(c, sl, sl.dev, n, nullptr, true, count, s, c->profile ? sl.sev.data() : nullptr);
     } else {
         HIP_TRY(hipMemsetAsync(sl.d_n + 1, 0, sizeof(uint32_t), s));
         for (uint32_t off = 0; off < n; off += kPlainChunk) {
             const uint32_t m = std::min(kPlainChunk, n - off);
             BatchDev v = sl.dev;
             v.recs += off; v.res += off; v.cells += off; v.seed += off; v.valid += off; v.tout += 2 * (size_t)off;
-            enqueue_kernels(c, sl, v, m, nullptr, false, count, s);
+            enqueue_kernels(c, sl, v, m, nullptr, false, count, s,
+                            c->profile ? sl.sev.data() + 9 * (size_t)(off / kPlainChunk) : nullptr);
             // chunk errors accumulate in the slot's error word
             launch_accum_errors(v, sl.d_n + 1, s);
         }
@@ -364,11 +419,36 @@ void run_batch(xdrop_ctx *c, Slot &sl, Ticket &t)
     }
     const uint32_t *err_src = c->mode == XDROP_MODE_PERSISTENT ? sl.dev.ctr + CtrLayout::kErrors : sl.d_n + 1;
     HIP_TRY(hipMemcpyAsync(sl.h_misc + 1, err_src, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    if (count && c->mode == XDROP_MODE_PERSISTENT)
+        HIP_TRY(hipMemcpyAsync(sl.h_stage, sl.dev.stage_sum, 16 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(sl.ev2, s));
     HIP_TRY(hipEventSynchronize(sl.ev2));
     float ms = 0.f;
     hipEventElapsedTime(&ms, sl.ev0, sl.ev1);
     t.dev_ms = ms;
+    if (c->profile) {
+        const size_t chunks = c->mode == XDROP_MODE_PLAIN ? (n + kPlainChunk - 1) / kPlainChunk : 1;
+        for (size_t ch = 0; ch < chunks; ++ch) {
+            hipEvent_t *e = sl.sev.data() + 9 * ch;
+            float a = 0.f;
+            hipEventElapsedTime(&a, e[0], e[1]);
+            t.stage_ms[XDROP_STAGE_INGEST] += a;
+            for (int q = 0; q < kWindowClasses; ++q) {
+                hipEventElapsedTime(&a, e[1 + q], e[2 + q]);
+                t.stage_ms[XDROP_STAGE_WINDOW0 + q] += a;
+            }
+            hipEventElapsedTime(&a, e[6], e[7]);
+            t.stage_ms[XDROP_STAGE_GENERIC] += a;
+            hipEventElapsedTime(&a, e[7], e[8]);
+            t.stage_ms[XDROP_STAGE_FINALIZE] += a;
+        }
+    }
+    if (count && c->mode == XDROP_MODE_PERSISTENT) {
+        for (int k = 0; k < XDROP_NUM_STAGES; ++k) {
+            t.stage_cells[k] = sl.h_stage[k];
+            t.stage_tasks[k] = sl.h_stage[8 + k];
+        }
+    }
     const uint32_t errors = sl.h_misc[1];
     if (!t.device) {
         std::memcpy(t.out, sl.h_res, (size_t)n * sizeof(xdrop_result));
@@ -560,6 +640,7 @@ xdrop_status xdrop_batch_create(const xdrop_config *cfg, xdrop_ctx **out)
     c->mode = cfg->mode;
     c->max_inflight = cfg->max_inflight ? cfg->max_inflight : 4;
     c->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (8ull << 30);
+    c->profile = (cfg->flags & XDROP_FLAG_PROFILE) != 0;
     c->tune = default_tuning();
     if (cfg->tuning_cache) {
         c->tuning_path = cfg->tuning_cache;
@@ -702,6 +783,11 @@ xdrop_status xdrop_batch_wait(xdrop_ctx *c, xdrop_ticket id, int64_t timeout_us,
         stats->queue_ms = t->t_admit - t->t_submit;
         stats->device_ms = t->dev_ms;
         stats->total_ms = t->t_done - t->t_submit;
+        for (int k = 0; k < XDROP_NUM_STAGES; ++k) {
+            stats->stage_ms[k] = t->stage_ms[k];
+            stats->stage_cells[k] = t->stage_cells[k];
+            stats->stage_tasks[k] = t->stage_tasks[k];
+        }
     }
     return t->status;
 }

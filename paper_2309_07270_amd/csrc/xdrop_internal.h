@@ -24,7 +24,7 @@ struct ReadInfo {
 struct TaskOut {
     int32_t score;
     int32_t i, j;
-    uint32_t status;   // 0 = done
+    uint32_t status;   // class that completed the task (stage index - 1)
     uint64_t cells;
 };
 
@@ -51,6 +51,7 @@ struct BatchDev {
     uint32_t *qkey;           // unsorted queue staging: (task id) per class, capacity 2*cap
     uint32_t *ctr;            // counters, see CtrLayout
     uint32_t *bucket_hist;    // kNumClasses * kNumBuckets
+    unsigned long long *stage_sum;  // [0..7] cells, [8..15] tasks completed per stage
     uint32_t cap;             // record capacity of the buffers
 };
 
@@ -91,6 +92,6 @@ void launch_window(int cls, const BatchDev &b, const StoreDev &st, uint32_t grid
                    bool count_cells, hipStream_t s);
 void launch_generic(const BatchDev &b, const StoreDev &st, int32_t *scratch, uint64_t scratch_stride,
                     uint32_t grid_waves, bool count_cells, hipStream_t s);
-void launch_finalize(const BatchDev &b, const StoreDev &st, uint32_t n, hipStream_t s);
+void launch_finalize(const BatchDev &b, const StoreDev &st, uint32_t n, bool stage_sums, hipStream_t s);
 
 }  // namespace xd

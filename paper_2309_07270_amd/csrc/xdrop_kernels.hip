@@ -164,11 +164,13 @@ __device__ __forceinline__ int bucket_of(uint32_t key)
 // ---------------------------------------------------------------------------
 // Counters reset (a kernel, so that it can sit inside a captured graph).
 // ---------------------------------------------------------------------------
-__global__ void reset_kernel(uint32_t *ctr, uint32_t *hist, const uint32_t *n_src, uint32_t n_imm)
+__global__ void reset_kernel(uint32_t *ctr, uint32_t *hist, unsigned long long *stage_sum, const uint32_t *n_src,
+                             uint32_t n_imm)
 {
     const int t = threadIdx.x;
     if (t < CtrLayout::kN) ctr[t] = 0;
     if (t == 0) ctr[CtrLayout::kN] = n_src ? *n_src : n_imm;
+    if (t < 16) stage_sum[t] = 0ull;
     for (int i = t; i < kNumClasses * kNumBuckets; i += blockDim.x) hist[i] = 0;
 }
 
@@ -480,7 +482,7 @@ __global__ void __launch_bounds__(256) window_kernel(BatchDev b, StoreDev st, in
         if (status == kStatusDone) {
             // every lane stores the same (wave-uniform) values
             TaskOut o;
-            o.score = w.T; o.i = w.bi; o.j = w.bj; o.status = kStatusDone; o.cells = w.cells;
+            o.score = w.T; o.i = w.bi; o.j = w.bj; o.status = (uint32_t)cls; o.cells = w.cells;
             b.tout[t] = o;
         } else {
             const uint32_t pos = wave_fetch_add(&b.ctr[CtrLayout::kCount + cls + 1], 1u);
@@ -559,7 +561,7 @@ __device__ void generic_run(const uint32_t *__restrict__ W, const Geo &g, int X,
         if (!live && prev_dead) break;
         prev_dead = !live;
     }
-    o.score = T; o.i = bi; o.j = bj; o.status = kStatusDone; o.cells = cells;
+    o.score = T; o.i = bi; o.j = bj; o.status = (uint32_t)kGenericClass; o.cells = cells;
 }
 
 template <bool COUNT>
@@ -585,11 +587,20 @@ __global__ void __launch_bounds__(256) generic_kernel(BatchDev b, StoreDev st, i
 // ---------------------------------------------------------------------------
 // Result write-back.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) finalize_kernel(BatchDev b, StoreDev st)
+__global__ void __launch_bounds__(256) finalize_kernel(BatchDev b, StoreDev st, int stage_sums)
 {
     const uint32_t n = b.ctr[CtrLayout::kN];
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
+    if (stage_sums && b.valid[r]) {
+        // per-stage totals: cells and extensions completed by each class
+        for (int s = 0; s < 2; ++s) {
+            const TaskOut o = b.tout[2 * r + s];
+            const int stg = 1 + (int)o.status;
+            atomicAdd(&b.stage_sum[stg], (unsigned long long)o.cells);
+            atomicAdd(&b.stage_sum[8 + stg], 1ull);
+        }
+    }
     xdrop_result out{};
     uint64_t c = 0;
     if (b.valid[r]) {
@@ -617,7 +628,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(BatchDev b, StoreDev st)
 // ---------------------------------------------------------------------------
 void launch_reset_n(const BatchDev &b, const uint32_t *n_src, uint32_t n_imm, hipStream_t s)
 {
-    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, s, b.ctr, b.bucket_hist, n_src, n_imm);
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, s, b.ctr, b.bucket_hist, b.stage_sum, n_src, n_imm);
 }
 
 void launch_accum_errors(const BatchDev &b, uint32_t *acc, hipStream_t s)
@@ -673,10 +684,10 @@ void launch_generic(const BatchDev &b, const StoreDev &st, int32_t *scratch, uin
         hipLaunchKernelGGL(generic_kernel<false>, dim3(blocks), dim3(256), 0, s, b, st, scratch, stride);
 }
 
-void launch_finalize(const BatchDev &b, const StoreDev &st, uint32_t n, hipStream_t s)
+void launch_finalize(const BatchDev &b, const StoreDev &st, uint32_t n, bool stage_sums, hipStream_t s)
 {
     const uint32_t blocks = (n + 255) / 256;
-    if (blocks) hipLaunchKernelGGL(finalize_kernel, dim3(blocks), dim3(256), 0, s, b, st);
+    if (blocks) hipLaunchKernelGGL(finalize_kernel, dim3(blocks), dim3(256), 0, s, b, st, stage_sums ? 1 : 0);
 }
 
 }  // namespace xd

@@ -35,15 +35,26 @@ class Config(ctypes.Structure):
     _fields_ = [("reads", ctypes.POINTER(ctypes.c_char_p)), ("lengths", ctypes.POINTER(ctypes.c_uint32)),
                 ("n_reads", ctypes.c_uint32), ("device", ctypes.c_int32), ("mode", ctypes.c_uint32),
                 ("max_inflight", ctypes.c_uint32), ("hbm_budget_bytes", ctypes.c_uint64),
-                ("tuning_cache", ctypes.c_char_p)]
+                ("tuning_cache", ctypes.c_char_p), ("flags", ctypes.c_uint32)]
+
+
+NUM_STAGES = 8
+STAGE_NAMES = ("ingest", "window64", "window128", "window192", "window256", "window1024", "generic", "finalize")
+FLAG_PROFILE = 1
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("records", ctypes.c_uint64), ("cells", ctypes.c_uint64), ("queue_ms", ctypes.c_double),
-                ("device_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+                ("device_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("stage_ms", ctypes.c_double * NUM_STAGES), ("stage_cells", ctypes.c_uint64 * NUM_STAGES),
+                ("stage_tasks", ctypes.c_uint64 * NUM_STAGES)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        out = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            out[k] = list(v) if hasattr(v, "__len__") else v
+        return out
 
 
 class XdropError(RuntimeError):
@@ -93,7 +104,7 @@ class Context:
     """One xdrop context: a device-resident read store plus batch execution."""
 
     def __init__(self, reads, device: int = 0, mode: int = MODE_PERSISTENT, max_inflight: int = 4,
-                 hbm_budget_bytes: int = 0, tuning_cache: str | None = None):
+                 hbm_budget_bytes: int = 0, tuning_cache: str | None = None, profile: bool = False):
         self.lib = load_library()
         if isinstance(reads, ReadStore):
             seqs = [ASCII[reads.read(r)].tobytes() for r in range(reads.n)]
@@ -103,7 +114,7 @@ class Context:
         arr = (ctypes.c_char_p * len(seqs))(*seqs)
         lens = (ctypes.c_uint32 * len(seqs))(*[len(s) for s in seqs])
         cfg = Config(arr, lens, len(seqs), device, mode, max_inflight, hbm_budget_bytes,
-                     tuning_cache.encode() if tuning_cache else None)
+                     tuning_cache.encode() if tuning_cache else None, FLAG_PROFILE if profile else 0)
         h = ctypes.c_void_p()
         st = self.lib.xdrop_batch_create(ctypes.byref(cfg), ctypes.byref(h))
         self._seqs = None

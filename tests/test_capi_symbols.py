@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     assert W.RECORD_DTYPE.itemsize == 32 and W.RESULT_DTYPE.itemsize == 32
-    assert ctypes.sizeof(X.Stats) == 8 + 8 + 3 * 8
+    assert ctypes.sizeof(X.Stats) == 8 + 8 + 3 * 8 + 3 * 8 * 8
     # field offsets of xdrop_record as declared
     offs = {n: W.RECORD_DTYPE.fields[n][1] for n in W.RECORD_DTYPE.names}
     assert offs == {"read_a": 0, "read_b": 4, "pos_a": 8, "pos_b": 12, "k": 16, "strand": 18, "pad": 19,
@@ -60,7 +60,7 @@ def test_create_rejects_bad_reads_before_touching_the_device():
     for reads in ([b"ACGN"], [b""], [b"ACGT", b"AC-T"]):
         arr = (ctypes.c_char_p * len(reads))(*reads)
         lens = (ctypes.c_uint32 * len(reads))(*[len(r) for r in reads])
-        cfg = X.Config(arr, lens, len(reads), 0, 0, 0, 0, None)
+        cfg = X.Config(arr, lens, len(reads), 0, 0, 0, 0, None, 0)
         h = ctypes.c_void_p()
         assert lib.xdrop_batch_create(ctypes.byref(cfg), ctypes.byref(h)) == X.XDROP_E_INVALID
         assert not h.value
