@@ -78,14 +78,18 @@ enum {
                                      (stats.stage_ms); adds ~1 us per stage  */
 };
 
-/* Kernel stages reported in xdrop_batch_stats.stage_ms / stage_cells. */
+/* Kernel stages reported in xdrop_batch_stats.stage_ms / stage_cells.  An
+ * extension runs in the adaptive kernel first and restarts in the next
+ * stage only when its live band outgrows the current one. */
 enum {
-    XDROP_STAGE_INGEST = 0,       /* counter reset, validation, seed, classes, bucketing */
-    XDROP_STAGE_WINDOW0 = 1,      /* register-window classes 0..4 (64, 128, 192, 256,
-                                     1024-cell windows)                      */
-    XDROP_STAGE_GENERIC = 6,      /* unbounded band kernel                  */
-    XDROP_STAGE_FINALIZE = 7,     /* result write-back                      */
-    XDROP_NUM_STAGES = 8
+    XDROP_STAGE_INGEST = 0,       /* counter reset, validation, seed, bucketing  */
+    XDROP_STAGE_ADAPTIVE = 1,     /* register window of 64..256 slots that
+                                     follows the band width                 */
+    XDROP_STAGE_WIDE1024 = 2,     /* register window of 1024 slots          */
+    XDROP_STAGE_WIDE2048 = 3,     /* register window of 2048 slots          */
+    XDROP_STAGE_GENERIC = 4,      /* unbounded band (global memory)         */
+    XDROP_STAGE_FINALIZE = 5,     /* result write-back                      */
+    XDROP_NUM_STAGES = 6
 };
 
 #define XDROP_MAX_READ_LEN (1u << 24)
@@ -164,6 +168,37 @@ xdrop_status xdrop_batch_wait(xdrop_ctx *c, xdrop_ticket t, int64_t timeout_us,
 
 /* Drain outstanding batches, then free everything.  NULL is a no-op. */
 xdrop_status xdrop_batch_destroy(xdrop_ctx *c);
+
+typedef struct {
+    int32_t grow_margin;          /* adaptive window: free slots per side after widening   */
+    int32_t shrink_margin;        /* adaptive window: narrow when the band fits C-1 cells
+                                     per lane with this many free slots per side (>= 1) */
+    int32_t waves_per_cu;         /* persistent grid: wavefronts per compute unit           */
+    int32_t buckets;              /* 1: order extensions longest-first; 0: arrival order   */
+    int32_t generic_waves;        /* grid of the unbounded-band kernel (multiple of 4)     */
+} xdrop_tuning;
+
+/* Current launch parameters of a context. */
+xdrop_status xdrop_get_tuning(const xdrop_ctx *c, xdrop_tuning *out);
+
+/* Replace the launch parameters; only while no batch is in flight
+ * (XDROP_E_BUSY otherwise).  Values are clamped to their valid ranges. */
+xdrop_status xdrop_set_tuning(xdrop_ctx *c, const xdrop_tuning *t);
+
+/* Autotuner: run the n host records (a representative sample, e.g. 10k-50k
+ * records) under a grid of launch parameters -- persistent grid size, length
+ * bucketing, adaptive window margins -- keep the fastest by device time and
+ * make it the context's tuning.  When cache_path is non-NULL the choice is
+ * written there (text, one "key value" per line) and later contexts created
+ * with cfg->tuning_cache = cache_path start from it.  *best_ms (nullable)
+ * gets the best device time.  Only while no batch is in flight. */
+xdrop_status xdrop_autotune(xdrop_ctx *c, const xdrop_record *recs, size_t n, const char *cache_path,
+                            double *best_ms);
+
+/* Device bytes that admitting a batch of n records takes from the context's
+ * HBM budget (buffers sized for the next power of two >= max(n, 1024),
+ * including the unbounded kernel's scratch).  0 for a NULL context. */
+uint64_t xdrop_batch_footprint(const xdrop_ctx *c, size_t n);
 
 /* Human-readable text of a status code (static storage). */
 const char *xdrop_status_string(xdrop_status s);

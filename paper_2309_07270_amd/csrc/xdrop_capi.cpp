@@ -129,7 +129,6 @@ struct xdrop_ctx {
     uint64_t used = 0;
     int cus = 256;
     bool profile = false;
-    std::atomic<bool> use_graph{true};
 
     // store
     uint32_t *d_words = nullptr;
@@ -170,13 +169,11 @@ namespace {
 Tuning default_tuning()
 {
     Tuning t{};
-    // start class by drop: the live band of a 15 %-error overlap is about 0.9 X
-    // cells wide on average and up to ~1.45 X at its widest.
-    const int32_t lim[kWindowClasses] = {24, 60, 100, 150, 0x7fffffff};
-    for (int q = 0; q < kWindowClasses; ++q) t.x_class_limit[q] = lim[q];
+    t.grow_margin = 8;
+    t.shrink_margin = 6;
     t.waves_per_cu = 32;
     t.buckets = 1;
-    t.generic_waves = 256;
+    t.generic_waves = 64;
     return t;
 }
 
@@ -186,8 +183,10 @@ bool load_tuning(const std::string &path, Tuning &t)
     if (!f) return false;
     std::string key;
     while (f >> key) {
-        if (key == "x_class_limit") {
-            for (int q = 0; q < kWindowClasses; ++q) f >> t.x_class_limit[q];
+        if (key == "grow_margin") {
+            f >> t.grow_margin;
+        } else if (key == "shrink_margin") {
+            f >> t.shrink_margin;
         } else if (key == "waves_per_cu") {
             f >> t.waves_per_cu;
         } else if (key == "buckets") {
@@ -296,8 +295,9 @@ void alloc_slot_buffers(xdrop_ctx *c, Slot &s, uint32_t cap)
     HIP_TRY(hipHostMalloc((void **)&s.h_misc, 64, hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void **)&s.h_stage, 16 * sizeof(unsigned long long), hipHostMallocDefault));
     if (c->profile) {
-        const size_t chunks = c->mode == XDROP_MODE_PLAIN ? (cap + kPlainChunk - 1) / kPlainChunk : 1;
-        s.sev.resize(9 * chunks, nullptr);
+        // plain form: one event set per chunk; persistent form: one set
+        const size_t sets = c->mode == XDROP_MODE_PLAIN ? (cap + kPlainChunk - 1) / kPlainChunk : 1;
+        s.sev.resize((kNumStages + 1) * sets, nullptr);
         for (auto &e : s.sev) HIP_TRY(hipEventCreate(&e));
     }
 }
@@ -320,7 +320,7 @@ uint32_t round_cap(size_t n)
 void enqueue_kernels(xdrop_ctx *c, Slot &sl, const BatchDev &b, uint32_t n, const uint32_t *n_src, bool persistent,
                      bool count, hipStream_t s, hipEvent_t *ev)
 {
-    // ev (nullable): 9 stage-boundary events recorded between the launches
+    // ev (nullable): kNumStages + 1 stage-boundary events recorded between the launches
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     launch_reset_n(b, n_src, n, s);
     const bool stage = persistent && c->tune.buckets > 0;
@@ -328,15 +328,17 @@ void enqueue_kernels(xdrop_ctx *c, Slot &sl, const BatchDev &b, uint32_t n, cons
     if (stage) launch_bucket(b, c->st, n, s);
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     const uint32_t resident = (uint32_t)c->cus * (uint32_t)std::max(1, c->tune.waves_per_cu);
-    for (int q = 0; q < kWindowClasses; ++q) {
-        uint32_t waves = persistent ? resident : std::max<uint32_t>(2 * n, 4);
-        launch_window(q, b, c->st, waves, count, s);
-        if (ev) HIP_TRY(hipEventRecord(ev[2 + q], s));
+    // plain form: one wavefront per extension for the first class
+    launch_adaptive(b, c->st, c->tune, persistent ? resident : std::max<uint32_t>(2 * n, 4), count, s);
+    if (ev) HIP_TRY(hipEventRecord(ev[2], s));
+    for (int w = 0; w < kWideClasses; ++w) {
+        launch_wide(w, b, c->st, (uint32_t)c->cus * 8u, count, s);
+        if (ev) HIP_TRY(hipEventRecord(ev[3 + w], s));
     }
     launch_generic(b, c->st, sl.scratch, sl.scratch_stride, sl.generic_waves, count, s);
-    if (ev) HIP_TRY(hipEventRecord(ev[7], s));
+    if (ev) HIP_TRY(hipEventRecord(ev[2 + kNumClasses - 1], s));
     launch_finalize(b, c->st, n, count, s);
-    if (ev) HIP_TRY(hipEventRecord(ev[8], s));
+    if (ev) HIP_TRY(hipEventRecord(ev[kNumStages], s));
 }
 
 // The persistent form's kernel sequence captured once per slot (and per cell
@@ -349,10 +351,10 @@ hipGraphExec_t get_graph(xdrop_ctx *c, Slot &sl, bool count)
     hipGraphExec_t &g = sl.graph[count ? 1 : 0];
     if (g) return g;
     hipGraph_t graph = nullptr;
+    (void)hipGetLastError();   // start the capture with no stale error
     HIP_TRY(hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal));
     try {
-        enqueue_kernels(c, sl, sl.dev, sl.cap, sl.d_n, true, count, sl.stream,
-                        c->profile ? sl.sev.data() : nullptr);
+        enqueue_kernels(c, sl, sl.dev, sl.cap, sl.d_n, true, count, sl.stream, nullptr);
     } catch (...) {
         hipStreamEndCapture(sl.stream, &graph);
         if (graph) hipGraphDestroy(graph);
@@ -383,19 +385,13 @@ void run_batch(xdrop_ctx *c, Slot &sl, Ticket &t)
     HIP_TRY(hipMemcpyAsync(sl.d_n, sl.h_misc, sizeof(uint32_t), hipMemcpyHostToDevice, s));
     HIP_TRY(hipEventRecord(sl.ev0, s));
     if (c->mode == XDROP_MODE_PERSISTENT) {
-        hipGraphExec_t g = nullptr;
-        if (c->use_graph) {
-            try {
-                g = get_graph(c, sl, count);
-            } catch (const std::exception &e) {
-                if (!c->profile) throw;
-                c->use_graph = false;   // profiling events could not be captured
-            }
-        }
-        if (g)
-            HIP_TRY(hipGraphLaunch(g, s));
+        // Profiling times each stage with HIP events between launches on this
+        // stream, so it launches the graph's kernel sequence directly (same
+        // kernels, grids and order); otherwise the captured graph runs.
+        if (!c->profile)
+            HIP_TRY(hipGraphLaunch(get_graph(c, sl, count), s));
         else
-            enqueue_kernels(c, sl, sl.dev, n, nullptr, true, count, s, c->profile ? sl.sev.data() : nullptr);
+            enqueue_kernels(c, sl, sl.dev, n, nullptr, true, count, s, sl.sev.data());
     } else {
         HIP_TRY(hipMemsetAsync(sl.d_n + 1, 0, sizeof(uint32_t), s));
         for (uint32_t off = 0; off < n; off += kPlainChunk) {
@@ -403,7 +399,7 @@ void run_batch(xdrop_ctx *c, Slot &sl, Ticket &t)
             BatchDev v = sl.dev;
             v.recs += off; v.res += off; v.cells += off; v.seed += off; v.valid += off; v.tout += 2 * (size_t)off;
             enqueue_kernels(c, sl, v, m, nullptr, false, count, s,
-                            c->profile ? sl.sev.data() + 9 * (size_t)(off / kPlainChunk) : nullptr);
+                            c->profile ? sl.sev.data() + (kNumStages + 1) * (size_t)(off / kPlainChunk) : nullptr);
             // chunk errors accumulate in the slot's error word
             launch_accum_errors(v, sl.d_n + 1, s);
         }
@@ -424,23 +420,18 @@ void run_batch(xdrop_ctx *c, Slot &sl, Ticket &t)
     HIP_TRY(hipEventRecord(sl.ev2, s));
     HIP_TRY(hipEventSynchronize(sl.ev2));
     float ms = 0.f;
-    hipEventElapsedTime(&ms, sl.ev0, sl.ev1);
+    HIP_TRY(hipEventElapsedTime(&ms, sl.ev0, sl.ev1));
     t.dev_ms = ms;
     if (c->profile) {
-        const size_t chunks = c->mode == XDROP_MODE_PLAIN ? (n + kPlainChunk - 1) / kPlainChunk : 1;
+        const bool plain = c->mode == XDROP_MODE_PLAIN;
+        const size_t chunks = plain ? (n + kPlainChunk - 1) / kPlainChunk : 1;
         for (size_t ch = 0; ch < chunks; ++ch) {
-            hipEvent_t *e = sl.sev.data() + 9 * ch;
-            float a = 0.f;
-            hipEventElapsedTime(&a, e[0], e[1]);
-            t.stage_ms[XDROP_STAGE_INGEST] += a;
-            for (int q = 0; q < kWindowClasses; ++q) {
-                hipEventElapsedTime(&a, e[1 + q], e[2 + q]);
-                t.stage_ms[XDROP_STAGE_WINDOW0 + q] += a;
+            hipEvent_t *e = sl.sev.data() + (kNumStages + 1) * (plain ? ch : 0);
+            for (int k = 0; k < kNumStages; ++k) {
+                float a = 0.f;
+                HIP_TRY(hipEventElapsedTime(&a, e[k], e[k + 1]));
+                t.stage_ms[k] += a;
             }
-            hipEventElapsedTime(&a, e[6], e[7]);
-            t.stage_ms[XDROP_STAGE_GENERIC] += a;
-            hipEventElapsedTime(&a, e[7], e[8]);
-            t.stage_ms[XDROP_STAGE_FINALIZE] += a;
         }
     }
     if (count && c->mode == XDROP_MODE_PERSISTENT) {
@@ -599,6 +590,53 @@ xdrop_status submit_common(xdrop_ctx *c, std::shared_ptr<Ticket> t, const xdrop_
     return XDROP_OK;
 }
 
+bool ctx_idle(xdrop_ctx *c)
+{
+    for (auto &sl : c->slots)
+        if (sl->busy) return false;
+    return true;
+}
+
+void clamp_tuning(Tuning &t)
+{
+    t.grow_margin = std::min(std::max(t.grow_margin, 1), 64);
+    t.shrink_margin = std::min(std::max(t.shrink_margin, 1), 64);
+    t.waves_per_cu = std::min(std::max(t.waves_per_cu, 1), 64);
+    t.buckets = t.buckets ? 1 : 0;
+    t.generic_waves = (std::min(std::max(t.generic_waves, 4), 4096) + 3) / 4 * 4;
+}
+
+// new launch parameters: captured graphs hold the old ones; the unbounded
+// kernel's scratch is sized by generic_waves (called with c->mu held, idle)
+void apply_tuning(xdrop_ctx *c, const Tuning &t)
+{
+    const bool rescratch = t.generic_waves != c->tune.generic_waves;
+    c->tune = t;
+    for (auto &sl : c->slots) {
+        for (auto &g : sl->graph)
+            if (g) { hipGraphExecDestroy(g); g = nullptr; }
+        if (rescratch && sl->cap) {
+            const uint32_t cap = sl->cap;
+            c->used -= sl->bytes;
+            free_slot_buffers(*sl);
+            alloc_slot_buffers(c, *sl, cap);
+            c->used += sl->bytes;
+        }
+    }
+}
+
+bool write_tuning(const std::string &path, const Tuning &t)
+{
+    std::ofstream f(path);
+    if (!f) return false;
+    f << "grow_margin " << t.grow_margin << "\n"
+      << "shrink_margin " << t.shrink_margin << "\n"
+      << "waves_per_cu " << t.waves_per_cu << "\n"
+      << "buckets " << t.buckets << "\n"
+      << "generic_waves " << t.generic_waves << "\n";
+    return (bool)f;
+}
+
 }  // namespace
 
 extern "C" {
@@ -646,6 +684,7 @@ xdrop_status xdrop_batch_create(const xdrop_config *cfg, xdrop_ctx **out)
         c->tuning_path = cfg->tuning_cache;
         load_tuning(c->tuning_path, c->tune);
     }
+    clamp_tuning(c->tune);
     // pack the store: fwd and reverse complement of every read, each starting
     // on a word boundary, 2 bits per base
     const uint32_t nr = cfg->n_reads;
@@ -790,6 +829,116 @@ xdrop_status xdrop_batch_wait(xdrop_ctx *c, xdrop_ticket id, int64_t timeout_us,
         }
     }
     return t->status;
+}
+
+xdrop_status xdrop_get_tuning(const xdrop_ctx *c, xdrop_tuning *out)
+{
+    if (!c || !out) return XDROP_E_INVALID;
+    out->grow_margin = c->tune.grow_margin;
+    out->shrink_margin = c->tune.shrink_margin;
+    out->waves_per_cu = c->tune.waves_per_cu;
+    out->buckets = c->tune.buckets;
+    out->generic_waves = c->tune.generic_waves;
+    return XDROP_OK;
+}
+
+xdrop_status xdrop_set_tuning(xdrop_ctx *c, const xdrop_tuning *in)
+{
+    if (!c || !in) return XDROP_E_INVALID;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (!ctx_idle(c)) return XDROP_E_BUSY;
+    Tuning t = c->tune;
+    t.grow_margin = in->grow_margin;
+    t.shrink_margin = in->shrink_margin;
+    t.waves_per_cu = in->waves_per_cu;
+    t.buckets = in->buckets;
+    t.generic_waves = in->generic_waves;
+    clamp_tuning(t);
+    try {
+        apply_tuning(c, t);
+    } catch (const std::exception &e) {
+        c->fail(e.what());
+        return XDROP_E_NOMEM;
+    }
+    return XDROP_OK;
+}
+
+xdrop_status xdrop_autotune(xdrop_ctx *c, const xdrop_record *recs, size_t n, const char *cache_path,
+                            double *best_ms)
+{
+    if (!c || !recs || n == 0) return XDROP_E_INVALID;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        if (!ctx_idle(c)) return XDROP_E_BUSY;
+    }
+    std::vector<xdrop_result> out(n);
+    auto time_once = [&](double &ms) -> xdrop_status {
+        xdrop_ticket tk;
+        xdrop_status st = xdrop_batch_submit(c, recs, n, out.data(), nullptr, -1, &tk);
+        if (st != XDROP_OK) return st;
+        xdrop_batch_stats s{};
+        st = xdrop_batch_wait(c, tk, -1, &s);
+        ms = s.device_ms;
+        return st;
+    };
+    std::vector<Tuning> grid;
+    const int wpc[] = {8, 16, 24, 32};
+    const int margins[][2] = {{4, 2}, {8, 4}, {8, 6}, {12, 8}, {16, 12}};
+    for (int w : wpc)
+        for (int b = 0; b <= 1; ++b)
+            for (auto &mg : margins) {
+                Tuning t = c->tune;
+                t.waves_per_cu = w;
+                t.buckets = b;
+                t.grow_margin = mg[0];
+                t.shrink_margin = mg[1];
+                grid.push_back(t);
+            }
+    const Tuning start = c->tune;
+    Tuning best = start;
+    double best_t = 1e300;
+    for (const Tuning &cand : grid) {
+        {
+            std::lock_guard<std::mutex> lk(c->mu);
+            try {
+                apply_tuning(c, cand);
+            } catch (const std::exception &e) {
+                c->fail(e.what());
+                return XDROP_E_NOMEM;
+            }
+        }
+        double ms0 = 0, ms1 = 0, ms2 = 0;
+        xdrop_status st = time_once(ms0);           // graph capture and warm-up
+        if (st == XDROP_OK) st = time_once(ms1);
+        if (st == XDROP_OK) st = time_once(ms2);
+        if (st != XDROP_OK) return st;
+        const double ms = std::min(ms1, ms2);
+        if (ms < best_t) {
+            best_t = ms;
+            best = cand;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        try {
+            apply_tuning(c, best);
+        } catch (const std::exception &e) {
+            c->fail(e.what());
+            return XDROP_E_NOMEM;
+        }
+        if (cache_path && !write_tuning(cache_path, best)) {
+            c->fail(std::string("cannot write tuning cache ") + cache_path);
+            return XDROP_E_INVALID;
+        }
+    }
+    if (best_ms) *best_ms = best_t;
+    return XDROP_OK;
+}
+
+uint64_t xdrop_batch_footprint(const xdrop_ctx *c, size_t n)
+{
+    if (!c) return 0;
+    return (uint64_t)slot_footprint(c, round_cap(n));
 }
 
 xdrop_status xdrop_batch_destroy(xdrop_ctx *c)

@@ -30,13 +30,19 @@ struct TaskOut {
 
 enum : uint32_t { kStatusDone = 0, kStatusOverflow = 1 };
 
-// Extension kernels, by band window.  Class q < kWindowClasses runs the
-// register-window kernel with kWindowC[q] cells per lane (window 64*C); the
-// last class is the unbounded global-memory kernel.
-constexpr int kWindowClasses = 5;
-constexpr int kWindowC[kWindowClasses] = {1, 2, 3, 4, 16};
-constexpr int kNumClasses = kWindowClasses + 1;
-constexpr int kGenericClass = kWindowClasses;
+// Extension kernels ("classes"), tried in order; a task whose live band
+// outgrows a class restarts in the next one:
+//   0  adaptive register window, 1..4 cells per lane (64..256 slots), the
+//      width following the band;
+//   1  fixed register window of 16 cells per lane (1024 slots);
+//   2  fixed register window of 32 cells per lane (2048 slots);
+//   3  unbounded band, anti-diagonals in global memory.
+constexpr int kAdaptiveClass = 0;
+constexpr int kWideClasses = 2;
+constexpr int kWideC[kWideClasses] = {16, 32};
+constexpr int kGenericClass = 1 + kWideClasses;
+constexpr int kNumClasses = kGenericClass + 1;
+constexpr int kNumStages = kNumClasses + 2;   // ingest, classes..., finalize
 constexpr int kNumBuckets = 64;
 
 // Device buffers of one batch (all device pointers).
@@ -51,7 +57,7 @@ struct BatchDev {
     uint32_t *qkey;           // unsorted queue staging: (task id) per class, capacity 2*cap
     uint32_t *ctr;            // counters, see CtrLayout
     uint32_t *bucket_hist;    // kNumClasses * kNumBuckets
-    unsigned long long *stage_sum;  // [0..7] cells, [8..15] tasks completed per stage
+    unsigned long long *stage_sum;  // [0..7] cells, [8..15] tasks completed per stage (1 + class)
     uint32_t cap;             // record capacity of the buffers
 };
 
@@ -75,7 +81,8 @@ struct StoreDev {
 
 // Tunable launch parameters (the autotuner picks them).
 struct Tuning {
-    int32_t x_class_limit[kWindowClasses];  // X <= limit -> start in that class
+    int32_t grow_margin;                    // adaptive: free slots per side after widening
+    int32_t shrink_margin;                  // adaptive: narrow when the band fits C-1 with this slack
     int32_t waves_per_cu;                   // persistent grid size per class kernel
     int32_t buckets;                        // 0: no length bucketing
     int32_t generic_waves;                  // grid of the unbounded kernel
@@ -88,8 +95,10 @@ void launch_accum_errors(const BatchDev &b, uint32_t *acc, hipStream_t s);
 void launch_prep(const BatchDev &b, const StoreDev &st, const Tuning &tu, uint32_t n,
                  bool stage, hipStream_t s);
 void launch_bucket(const BatchDev &b, const StoreDev &st, uint32_t n, hipStream_t s);
-void launch_window(int cls, const BatchDev &b, const StoreDev &st, uint32_t grid_waves,
-                   bool count_cells, hipStream_t s);
+void launch_adaptive(const BatchDev &b, const StoreDev &st, const Tuning &tu, uint32_t grid_waves,
+                     bool count_cells, hipStream_t s);
+void launch_wide(int which, const BatchDev &b, const StoreDev &st, uint32_t grid_waves, bool count_cells,
+                 hipStream_t s);
 void launch_generic(const BatchDev &b, const StoreDev &st, int32_t *scratch, uint64_t scratch_stride,
                     uint32_t grid_waves, bool count_cells, hipStream_t s);
 void launch_finalize(const BatchDev &b, const StoreDev &st, uint32_t n, bool stage_sums, hipStream_t s);

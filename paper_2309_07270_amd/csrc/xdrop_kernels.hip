@@ -59,16 +59,29 @@ __device__ __forceinline__ uint32_t code_at(const uint32_t *__restrict__ W, uint
     return (W[p >> 4] >> ((p & 15) * 2)) & 3u;
 }
 
-// 32 codes starting at base p (clamped into the store), code t at bits 2t.
-__device__ __forceinline__ uint64_t load32(const uint32_t *__restrict__ W, int64_t p, int64_t maxp)
+// 16*NW codes starting at base p (clamped into the store): code t at bits
+// 2*(t & 15) of out[t >> 4].  Reads NW+1 words; the store keeps guard words
+// after its last base so that any clamped p stays inside it.
+template <int NW>
+__device__ __forceinline__ void load_codes(const uint32_t *__restrict__ W, int64_t p, int64_t maxp,
+                                           uint32_t (&out)[NW])
 {
     p = p < 0 ? 0 : (p > maxp ? maxp : p);
     const uint64_t w = (uint64_t)p >> 4;
     const uint32_t sh = (uint32_t)(p & 15) * 2u;
-    const uint32_t w0 = W[w], w1 = W[w + 1], w2 = W[w + 2];
-    const uint32_t lo = __builtin_amdgcn_alignbit(w1, w0, sh);
-    const uint32_t hi = __builtin_amdgcn_alignbit(w2, w1, sh);
-    return ((uint64_t)hi << 32) | lo;
+    uint32_t raw[NW + 1];
+#pragma unroll
+    for (int i = 0; i <= NW; ++i) raw[i] = W[w + i];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) out[i] = __builtin_amdgcn_alignbit(raw[i + 1], raw[i], sh);
+}
+
+// 16 codes starting at code f (compile-time) of a loaded window
+template <int NW>
+__device__ __forceinline__ uint32_t codes16(const uint32_t (&w)[NW], int f)
+{
+    const int q = f >> 4, r = f & 15;
+    return r == 0 ? w[q] : __builtin_amdgcn_alignbit(w[q + 1], w[q], 2u * (uint32_t)r);
 }
 
 struct Geo {
@@ -205,9 +218,7 @@ __global__ void __launch_bounds__(256) prep_kernel(BatchDev b, StoreDev st, Tuni
         for (uint32_t t = 0; t < R.k; ++t)
             s += code_at(st.words, A.fwd + R.pos_a + t) == code_at(st.words, bseed + t) ? R.match : R.mismatch;
         b.seed[r] = s;
-        cls = kGenericClass;
-        for (int q = kWindowClasses - 1; q >= 0; --q)
-            if (R.x <= tu.x_class_limit[q]) cls = q;
+        cls = kAdaptiveClass;
         key0 = min(R.pos_a, pb);
         key1 = min(A.len - R.pos_a - R.k, B.len - pb - R.k);
     }
@@ -270,23 +281,81 @@ __global__ void __launch_bounds__(256) bucket_scatter_kernel(BatchDev b, StoreDe
 // ---------------------------------------------------------------------------
 // Register-window X-drop extension.
 // ---------------------------------------------------------------------------
-template <int C, bool COUNT>
+
+// Wave-uniform state of one extension; it survives changes of window width.
+struct XState {
+    int d;          // next anti-diagonal to compute
+    int base;       // o_d = base + floor(d/2): i of slot 0 on anti-diagonal d
+    int T, bi, bj;  // best score so far and its cell
+    uint64_t cells;
+    int mn, mx;     // live slots over the last two anti-diagonals (on kGrow / kShrink)
+};
+
+constexpr int WMAX = 256;   // widest window of the adaptive kernel (C = 4): LDS slots per array
+enum : uint32_t { kDone = 0, kGrow = 1, kShrink = 2 };
+
+template <int C, bool COUNT, bool MA1, int STRIDE = WMAX>
 struct Window {
     static constexpr int WIN = 64 * C;
+    static constexpr int NWC = (C + UMAX + 16) / 16;   // words of codes per lane and block
+    static_assert(STRIDE >= WIN, "LDS stride must hold the window");
 
-    int Z1[C];                // anti-diagonal d-1 (Z units)
+    int Z1[C];                // anti-diagonal d-1 (Z units: S + |gap| * d; NEG = dead)
     int Z2[C];                // anti-diagonal d-2
     uint32_t mmo[C], mme[C];  // mismatch bit (bit 2u) of pair u, odd / even anti-diagonal
 
-    // wave-uniform state
-    int base;                 // o_d = base + floor(d/2): i of slot 0 on anti-diagonal d
-    int T, bi, bj;
-    uint64_t cells;
+    // fresh extension: only (0,0) live, in the middle slot
+    __device__ __forceinline__ void init(XState &s)
+    {
+        const int lane = lane_id();
+        const int s0 = WIN / 2 - 1;
+        s.base = -s0;
+        s.d = 1;
+        s.T = 0; s.bi = 0; s.bj = 0; s.cells = 0;
+        s.mn = s.mx = s0;
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            Z1[r] = (C * lane + r == s0) ? 0 : NEG;
+            Z2[r] = NEG;
+        }
+    }
+
+    // window contents -> LDS, by slot
+    __device__ __forceinline__ void save(int *lds) const
+    {
+        const int lane = lane_id();
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            lds[C * lane + r] = Z1[r];
+            lds[STRIDE + C * lane + r] = Z2[r];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
+    // take over a window of from_win slots saved in LDS: new slot s holds old slot s + delta
+    __device__ __forceinline__ void load(const int *lds, int from_win, int delta)
+    {
+        const int lane = lane_id();
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            const int s = C * lane + r + delta;
+            const bool ok = s >= 0 && s < from_win;
+            const int sc = ok ? s : 0;
+            const int a = lds[sc], b2 = lds[STRIDE + sc];
+            Z1[r] = ok ? a : NEG;
+            Z2[r] = ok ? b2 : NEG;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
 
     // One anti-diagonal d (ODD = d & 1).  thr_p / thr_i: drop and improvement
     // thresholds of d in Z units (T_{d-1} - X and T_{d-1}, plus |gap| * d).
     template <bool ODD, bool BOUNDS>
-    __device__ __forceinline__ void step(int d, uint32_t ubit, int thr_p, int thr_i, int sm, int diff, int ma,
+    __device__ __forceinline__ void step(XState &s, int d, uint32_t ubit, int thr_p, int thr_i, int sm, int nd,
                                          int G, int m, int n)
     {
         const int lane = lane_id();
@@ -304,7 +373,7 @@ struct Window {
         }
         int lo_s = 0, hi_s = 0;
         if (BOUNDS) {
-            const int o = base + (d >> 1);
+            const int o = s.base + (d >> 1);
             lo_s = max(0, d - n) - o;
             hi_s = min(m, d) - o;
         }
@@ -314,21 +383,22 @@ struct Window {
         for (int r = 0; r < C; ++r) {
             const uint32_t mm = ODD ? mmo[r] : mme[r];
             const int bit = (int)__builtin_amdgcn_ubfe(mm, ubit, 1u);
-            v[r] = max(t[r], (Z2[r] + sm) - bit * diff);
-            const int s = C * lane + r;
-            const bool inb = !BOUNDS || (s >= lo_s && s <= hi_s);
+            const int sig = __mul24(bit, nd) + sm;          // sigma - 2*gap
+            v[r] = max(t[r], Z2[r] + sig);
+            const int sl = C * lane + r;
+            const bool inb = !BOUNDS || (sl >= lo_s && sl <= hi_s);
             imp |= ballot(inb && v[r] > thr_i);
-            if (COUNT) cells += (uint64_t)__builtin_popcountll(ballot(inb && v[r] > NEG_HALF));
+            if (COUNT) s.cells += (uint64_t)__builtin_popcountll(ballot(inb && v[r] > NEG_HALF));
             t[r] = (inb && v[r] >= thr_p) ? v[r] : NEG;
         }
         if (imp) {
-            int vmax = thr_i + 1;
-            if (ma != 1) {
+            int vmax = thr_i + 1;   // match weight 1: any improving cell holds exactly T + 1
+            if (!MA1) {
                 int lm = NEG;
 #pragma unroll
                 for (int r = 0; r < C; ++r) {
-                    const int s = C * lane + r;
-                    const bool inb = !BOUNDS || (s >= lo_s && s <= hi_s);
+                    const int sl = C * lane + r;
+                    const bool inb = !BOUNDS || (sl >= lo_s && sl <= hi_s);
                     lm = max(lm, inb ? v[r] : NEG);
                 }
                 vmax = uni(wave_max(lm));
@@ -337,16 +407,16 @@ struct Window {
             int rl = C;
 #pragma unroll
             for (int r = C - 1; r >= 0; --r) {
-                const int s = C * lane + r;
-                const bool inb = !BOUNDS || (s >= lo_s && s <= hi_s);
+                const int sl = C * lane + r;
+                const bool inb = !BOUNDS || (sl >= lo_s && sl <= hi_s);
                 if (inb && v[r] == vmax) rl = r;
             }
             const uint64_t any = ballot(rl < C);
             const int l = __builtin_ctzll(any);
             const int rr = __builtin_amdgcn_readlane(rl, l);
-            T = vmax - G * d;
-            bi = base + (d >> 1) + C * l + rr;
-            bj = d - bi;
+            s.T = vmax - G * d;
+            s.bi = s.base + (d >> 1) + C * l + rr;
+            s.bj = d - s.bi;
         }
 #pragma unroll
         for (int r = 0; r < C; ++r) {
@@ -371,118 +441,203 @@ struct Window {
         return mx >= 0;
     }
 
-    // shift the window by delta slots: new slot s holds old slot s + delta
-    __device__ void recenter(int delta, int *lds)
-    {
-        const int lane = lane_id();
-#pragma unroll
-        for (int r = 0; r < C; ++r) {
-            lds[C * lane + r] = Z1[r];
-            lds[WIN + C * lane + r] = Z2[r];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-        for (int r = 0; r < C; ++r) {
-            const int s = C * lane + r + delta;
-            const bool ok = s >= 0 && s < WIN;
-            const int sc = ok ? s : 0;
-            const int a = lds[sc], b2 = lds[WIN + sc];
-            Z1[r] = ok ? a : NEG;
-            Z2[r] = ok ? b2 : NEG;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        base += delta;
-    }
-
-    // Run one extension.  Returns kStatusDone or kStatusOverflow.
+    // Advance the extension block by block.  Returns kDone, or kGrow / kShrink
+    // with the window saved to LDS and s.mn / s.mx set (shrink_width < 0: never).
     __device__ uint32_t run(const uint32_t *__restrict__ W, int64_t maxp, const Geo &g, int X, int ma, int mi,
-                            int gap, int *lds)
+                            int gap, int *lds, XState &s, int shrink_width)
     {
         const int lane = lane_id();
         const int m = g.m, n = g.n;
         const int G = -gap;
         const int sm = ma + 2 * G;          // sigma(match) - 2*gap
-        const int diff = ma - mi;           // match - mismatch
-        const int s0 = WIN / 2 - 1;
-        base = -s0;                         // cell (0,0) in slot s0
-        T = 0; bi = 0; bj = 0; cells = 0;
-#pragma unroll
-        for (int r = 0; r < C; ++r) {
-            Z1[r] = (C * lane + r == s0) ? 0 : NEG;
-            Z2[r] = NEG;
-        }
+        const int nd = mi - ma;             // mismatch - match
         const int dend = m + n;
-        int d = 1;
-        while (d <= dend) {
+        while (s.d <= dend) {
             int mn, mx;
             if (!band(mn, mx)) break;                 // two dead anti-diagonals
             const int width = mx - mn + 1;
-            if (width + 2 > WIN) return kStatusOverflow;
+            if (width + 2 > WIN || width <= shrink_width) {
+                save(lds);
+                s.mn = mn;
+                s.mx = mx;
+                return width + 2 > WIN ? kGrow : kShrink;
+            }
+            const int d = s.d;
             int U = min(UMAX, (WIN - width) / 2);
             U = min(U, (dend - d + 2) >> 1);
-            if (mn < U || mx > WIN - 1 - U) recenter(mn - (WIN - width) / 2, lds);
-            // codes for this block: a from A0 + C*lane, b from B0 - C*lane - (C-1)
+            if (mn < U || mx > WIN - 1 - U) {
+                const int delta = mn - (WIN - width) / 2;
+                save(lds);
+                load(lds, WIN, delta);
+                s.base += delta;
+            }
+            // codes for this block: slot r of this lane meets a[A0 + C*lane + r + u
+            // (+1 on even d)] and b[B0 - C*lane - r + u] at pair u
             const int e0 = (d - 1) >> 1;
-            const int64_t A0 = (int64_t)base + e0 - 1;
-            const int64_t B0 = (int64_t)e0 - base;
-            const uint64_t aw = load32(W, (int64_t)g.abase + A0 + C * lane, maxp);
-            const uint64_t bw = load32(W, (int64_t)g.bbase + B0 - C * lane - (C - 1), maxp);
+            const int64_t A0 = (int64_t)s.base + e0 - 1;
+            const int64_t B0 = (int64_t)e0 - s.base;
+            uint32_t aw[NWC], bw[NWC];
+            load_codes<NWC>(W, (int64_t)g.abase + A0 + C * lane, maxp, aw);
+            load_codes<NWC>(W, (int64_t)g.bbase + B0 - C * lane - (C - 1), maxp, bw);
 #pragma unroll
             for (int r = 0; r < C; ++r) {
-                const uint32_t bb = (uint32_t)(bw >> (2 * (C - 1 - r)));
-                const uint32_t xo = (uint32_t)(aw >> (2 * r)) ^ bb;
-                const uint32_t xe = (uint32_t)(aw >> (2 * (r + 1))) ^ bb;
+                const uint32_t bb = codes16<NWC>(bw, C - 1 - r);
+                const uint32_t xo = codes16<NWC>(aw, r) ^ bb;
+                const uint32_t xe = codes16<NWC>(aw, r + 1) ^ bb;
                 mmo[r] = (xo | (xo >> 1)) & 0x55555555u;
                 mme[r] = (xe | (xe >> 1)) & 0x55555555u;
             }
             const int dlast = d + 2 * U - 1;
-            const int o_first = base + (d >> 1), o_last = base + (dlast >> 1);
+            const int o_first = s.base + (d >> 1), o_last = s.base + (dlast >> 1);
             const bool fast = o_first >= 0 && o_last >= dlast - n && o_last + WIN - 1 <= m &&
                               o_first + WIN - 1 <= d;
             if (fast) {
                 for (int u = 0; u < U; ++u) {
                     const int dd = d + 2 * u;
                     const uint32_t ub = 2u * (uint32_t)u;
-                    step<true, false>(dd, ub, T - X + G * dd, T + G * dd, sm, diff, ma, G, m, n);
-                    step<false, false>(dd + 1, ub, T - X + G * (dd + 1), T + G * (dd + 1), sm, diff, ma, G, m, n);
+                    step<true, false>(s, dd, ub, s.T - X + G * dd, s.T + G * dd, sm, nd, G, m, n);
+                    step<false, false>(s, dd + 1, ub, s.T - X + G * (dd + 1), s.T + G * (dd + 1), sm, nd, G, m, n);
                 }
             } else {
                 for (int u = 0; u < U; ++u) {
                     const int dd = d + 2 * u;
                     const uint32_t ub = 2u * (uint32_t)u;
-                    step<true, true>(dd, ub, T - X + G * dd, T + G * dd, sm, diff, ma, G, m, n);
-                    step<false, true>(dd + 1, ub, T - X + G * (dd + 1), T + G * (dd + 1), sm, diff, ma, G, m, n);
+                    step<true, true>(s, dd, ub, s.T - X + G * dd, s.T + G * dd, sm, nd, G, m, n);
+                    step<false, true>(s, dd + 1, ub, s.T - X + G * (dd + 1), s.T + G * (dd + 1), sm, nd, G, m, n);
                 }
             }
-            d += 2 * U;
+            s.d = d + 2 * U;
         }
-        return kStatusDone;
+        return kDone;
     }
 };
 
-template <int C, bool COUNT>
-__global__ void __launch_bounds__(256) window_kernel(BatchDev b, StoreDev st, int cls)
+template <int C, bool COUNT, bool MA1>
+using WideWindow = Window<C, COUNT, MA1, 64 * C>;
+
+// Smallest adaptive width (cells per lane) whose window holds `width` live
+// slots with `margin` slots of slack on each side; 0 if none does.
+__device__ __forceinline__ int fit_c(int width, int margin)
 {
-    extern __shared__ int lds_all[];
-    const int wave = threadIdx.x >> 6;
-    int *lds = lds_all + wave * (2 * 64 * C);
+#pragma unroll
+    for (int c = 1; c <= 4; ++c)
+        if (width + 2 * margin <= 64 * c) return c;
+    return 0;
+}
+
+// One extension with a window that widens and narrows with its band:
+// C = 1..4 cells per lane, the live band handed over through LDS.  Returns
+// false if the band outgrew the widest window (the task then restarts in the
+// next class).
+template <bool COUNT, bool MA1>
+__device__ bool run_adaptive(const uint32_t *__restrict__ W, int64_t maxp, const Task &k, int *lds, XState &s,
+                             int grow_margin, int shrink_margin)
+{
+    // margins >= 1: a band that was just narrowed fits its new window with a
+    // free slot on each side, so it cannot be widened again before a block runs
+    grow_margin = max(grow_margin, 1);
+    shrink_margin = max(shrink_margin, 1);
+    int C = 1, from_win = 0, delta = 0;
+    bool fresh = true;
+    for (;;) {
+        // narrow back once the band fits the next smaller window with shrink_margin to spare
+        const int shrink_width = C > 1 ? 64 * (C - 1) - 2 * shrink_margin : -1;
+        uint32_t st;
+        switch (C) {
+        case 1: {
+            Window<1, COUNT, MA1> w;
+            if (fresh) w.init(s); else w.load(lds, from_win, delta);
+            st = w.run(W, maxp, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
+        } break;
+        case 2: {
+            Window<2, COUNT, MA1> w;
+            if (fresh) w.init(s); else w.load(lds, from_win, delta);
+            st = w.run(W, maxp, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
+        } break;
+        case 3: {
+            Window<3, COUNT, MA1> w;
+            if (fresh) w.init(s); else w.load(lds, from_win, delta);
+            st = w.run(W, maxp, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
+        } break;
+        default: {
+            Window<4, COUNT, MA1> w;
+            if (fresh) w.init(s); else w.load(lds, from_win, delta);
+            st = w.run(W, maxp, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
+        } break;
+        }
+        if (st == kDone) return true;
+        fresh = false;
+        const int width = s.mx - s.mn + 1;
+        int nc;
+        if (st == kGrow) {
+            nc = fit_c(width, grow_margin);
+            if (nc == 0) nc = fit_c(width, 1);
+            if (nc == 0) return false;
+        } else {
+            nc = C - 1;
+        }
+        from_win = 64 * C;
+        delta = s.mn - (64 * nc - width) / 2;
+        s.base += delta;
+        C = nc;
+    }
+}
+
+// Class 0: adaptive windows.  Tasks whose band outgrows 256 cells go to class 1.
+template <bool COUNT>
+__global__ void __launch_bounds__(256) adaptive_kernel(BatchDev b, StoreDev st, int grow_margin, int shrink_margin)
+{
+    __shared__ int lds_all[4][2 * WMAX];
+    int *lds = lds_all[threadIdx.x >> 6];
+    const int cls = 0;
     const uint32_t qcap = 2u * b.cap;
     const uint32_t cnt = b.ctr[CtrLayout::kCount + cls];
-    Window<C, COUNT> w;
     for (;;) {
         const uint32_t idx = wave_fetch_add(&b.ctr[CtrLayout::kHead + cls], 1u);
         if (idx >= cnt) break;
         const uint32_t t = (uint32_t)uni((int)b.qbuf[cls * qcap + idx]);
         const Task k = load_task(b.recs, st.reads, t);
-        const uint32_t status = w.run(st.words, st.max_base, k.g, k.x, k.ma, k.mi, k.gap, lds);
-        if (status == kStatusDone) {
-            // every lane stores the same (wave-uniform) values
+        XState s;
+        const bool ok = k.ma == 1 ? run_adaptive<COUNT, true>(st.words, st.max_base, k, lds, s, grow_margin, shrink_margin)
+                                  : run_adaptive<COUNT, false>(st.words, st.max_base, k, lds, s, grow_margin, shrink_margin);
+        if (ok) {
+            TaskOut o;   // every lane stores the same (wave-uniform) values
+            o.score = s.T; o.i = s.bi; o.j = s.bj; o.status = (uint32_t)cls; o.cells = s.cells;
+            b.tout[t] = o;
+        } else {
+            const uint32_t pos = wave_fetch_add(&b.ctr[CtrLayout::kCount + cls + 1], 1u);
+            b.qbuf[(cls + 1) * qcap + pos] = t;
+        }
+    }
+}
+
+// Fixed wide window (C cells per lane) for bands the adaptive kernel cannot hold.
+template <int C, bool COUNT>
+__global__ void __launch_bounds__(256) wide_kernel(BatchDev b, StoreDev st, int cls)
+{
+    extern __shared__ int lds_wide[];
+    int *lds = lds_wide + (threadIdx.x >> 6) * (2 * 64 * C);
+    const uint32_t qcap = 2u * b.cap;
+    const uint32_t cnt = b.ctr[CtrLayout::kCount + cls];
+    for (;;) {
+        const uint32_t idx = wave_fetch_add(&b.ctr[CtrLayout::kHead + cls], 1u);
+        if (idx >= cnt) break;
+        const uint32_t t = (uint32_t)uni((int)b.qbuf[cls * qcap + idx]);
+        const Task k = load_task(b.recs, st.reads, t);
+        XState s;
+        uint32_t status;
+        if (k.ma == 1) {
+            WideWindow<C, COUNT, true> w;
+            w.init(s);
+            status = w.run(st.words, st.max_base, k.g, k.x, k.ma, k.mi, k.gap, lds, s, -1);
+        } else {
+            WideWindow<C, COUNT, false> w;
+            w.init(s);
+            status = w.run(st.words, st.max_base, k.g, k.x, k.ma, k.mi, k.gap, lds, s, -1);
+        }
+        if (status == kDone) {
             TaskOut o;
-            o.score = w.T; o.i = w.bi; o.j = w.bj; o.status = (uint32_t)cls; o.cells = w.cells;
+            o.score = s.T; o.i = s.bi; o.j = s.bj; o.status = (uint32_t)cls; o.cells = s.cells;
             b.tout[t] = o;
         } else {
             const uint32_t pos = wave_fetch_add(&b.ctr[CtrLayout::kCount + cls + 1], 1u);
@@ -649,29 +804,34 @@ void launch_bucket(const BatchDev &b, const StoreDev &st, uint32_t n, hipStream_
     if (blocks) hipLaunchKernelGGL(bucket_scatter_kernel, dim3(blocks), dim3(256), 0, s, b, st);
 }
 
+void launch_adaptive(const BatchDev &b, const StoreDev &st, const Tuning &tu, uint32_t grid_waves, bool count_cells,
+                     hipStream_t s)
+{
+    const uint32_t blocks = (grid_waves + 3) / 4;
+    if (count_cells)
+        hipLaunchKernelGGL(adaptive_kernel<true>, dim3(blocks), dim3(256), 0, s, b, st, tu.grow_margin, tu.shrink_margin);
+    else
+        hipLaunchKernelGGL(adaptive_kernel<false>, dim3(blocks), dim3(256), 0, s, b, st, tu.grow_margin, tu.shrink_margin);
+}
+
 template <int C>
-static void launch_window_c(const BatchDev &b, const StoreDev &st, int cls, uint32_t grid_waves, bool count,
-                            hipStream_t s)
+static void launch_wide_c(const BatchDev &b, const StoreDev &st, int cls, uint32_t grid_waves, bool count,
+                          hipStream_t s)
 {
     const uint32_t blocks = (grid_waves + 3) / 4;
     const size_t lds = 4 * 2 * 64 * C * sizeof(int);
     if (count)
-        hipLaunchKernelGGL((window_kernel<C, true>), dim3(blocks), dim3(256), lds, s, b, st, cls);
+        hipLaunchKernelGGL((wide_kernel<C, true>), dim3(blocks), dim3(256), lds, s, b, st, cls);
     else
-        hipLaunchKernelGGL((window_kernel<C, false>), dim3(blocks), dim3(256), lds, s, b, st, cls);
+        hipLaunchKernelGGL((wide_kernel<C, false>), dim3(blocks), dim3(256), lds, s, b, st, cls);
 }
 
-void launch_window(int cls, const BatchDev &b, const StoreDev &st, uint32_t grid_waves, bool count_cells,
-                   hipStream_t s)
+void launch_wide(int which, const BatchDev &b, const StoreDev &st, uint32_t grid_waves, bool count_cells,
+                 hipStream_t s)
 {
-    switch (kWindowC[cls]) {
-    case 1: launch_window_c<1>(b, st, cls, grid_waves, count_cells, s); break;
-    case 2: launch_window_c<2>(b, st, cls, grid_waves, count_cells, s); break;
-    case 3: launch_window_c<3>(b, st, cls, grid_waves, count_cells, s); break;
-    case 4: launch_window_c<4>(b, st, cls, grid_waves, count_cells, s); break;
-    case 16: launch_window_c<16>(b, st, cls, grid_waves, count_cells, s); break;
-    default: break;
-    }
+    static_assert(kWideC[0] == 16 && kWideC[1] == 32, "wide classes");
+    if (which == 0) launch_wide_c<16>(b, st, 1 + which, grid_waves, count_cells, s);
+    else launch_wide_c<32>(b, st, 1 + which, grid_waves, count_cells, s);
 }
 
 void launch_generic(const BatchDev &b, const StoreDev &st, int32_t *scratch, uint64_t stride, uint32_t grid_waves,

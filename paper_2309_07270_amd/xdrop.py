@@ -28,7 +28,8 @@ MODE_PLAIN = 1
 MAX_X = 1 << 30
 
 EXPORTED = ("xdrop_batch_create", "xdrop_batch_submit", "xdrop_batch_submit_device", "xdrop_batch_wait",
-            "xdrop_batch_destroy", "xdrop_status_string", "xdrop_last_error")
+            "xdrop_batch_destroy", "xdrop_batch_footprint", "xdrop_get_tuning", "xdrop_set_tuning",
+            "xdrop_autotune", "xdrop_status_string", "xdrop_last_error")
 
 
 class Config(ctypes.Structure):
@@ -38,8 +39,8 @@ class Config(ctypes.Structure):
                 ("tuning_cache", ctypes.c_char_p), ("flags", ctypes.c_uint32)]
 
 
-NUM_STAGES = 8
-STAGE_NAMES = ("ingest", "window64", "window128", "window192", "window256", "window1024", "generic", "finalize")
+NUM_STAGES = 6
+STAGE_NAMES = ("ingest", "adaptive", "wide1024", "wide2048", "generic", "finalize")
 FLAG_PROFILE = 1
 
 
@@ -55,6 +56,15 @@ class Stats(ctypes.Structure):
             v = getattr(self, k)
             out[k] = list(v) if hasattr(v, "__len__") else v
         return out
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("grow_margin", ctypes.c_int32), ("shrink_margin", ctypes.c_int32),
+                ("waves_per_cu", ctypes.c_int32), ("buckets", ctypes.c_int32),
+                ("generic_waves", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class XdropError(RuntimeError):
@@ -85,6 +95,13 @@ def load_library(path: str = LIB_PATH):
     lib.xdrop_status_string.restype = ctypes.c_char_p
     lib.xdrop_last_error.argtypes = [vp]
     lib.xdrop_last_error.restype = ctypes.c_char_p
+    lib.xdrop_batch_footprint.argtypes = [vp, ctypes.c_size_t]
+    lib.xdrop_batch_footprint.restype = ctypes.c_uint64
+    lib.xdrop_get_tuning.argtypes = [vp, P(Tuning)]
+    lib.xdrop_set_tuning.argtypes = [vp, P(Tuning)]
+    lib.xdrop_autotune.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_char_p, P(ctypes.c_double)]
+    for f in ("xdrop_get_tuning", "xdrop_set_tuning", "xdrop_autotune"):
+        getattr(lib, f).restype = ctypes.c_int
     for f in ("xdrop_batch_create", "xdrop_batch_submit", "xdrop_batch_submit_device", "xdrop_batch_wait",
               "xdrop_batch_destroy"):
         getattr(lib, f).restype = ctypes.c_int
@@ -139,6 +156,27 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def footprint(self, n: int) -> int:
+        """Device bytes a batch of n records takes from the HBM budget."""
+        return int(self.lib.xdrop_batch_footprint(self.h, n))
+
+    def tuning(self) -> dict:
+        t = Tuning()
+        self._check(self.lib.xdrop_get_tuning(self.h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        t = Tuning(**{**self.tuning(), **kw})
+        self._check(self.lib.xdrop_set_tuning(self.h, ctypes.byref(t)))
+
+    def autotune(self, recs: np.ndarray, cache_path: str | None = None) -> tuple:
+        """Sweep launch parameters on a sample batch; returns (tuning, best device ms)."""
+        recs = np.ascontiguousarray(recs, dtype=RECORD_DTYPE)
+        best = ctypes.c_double()
+        self._check(self.lib.xdrop_autotune(self.h, _ptr(recs), recs.size,
+                                            cache_path.encode() if cache_path else None, ctypes.byref(best)))
+        return self.tuning(), best.value
 
     def error(self) -> str:
         return self.lib.xdrop_last_error(self.h).decode()

@@ -161,3 +161,20 @@ def test_invalid_and_empty(xd, c0):
         assert e.value.status == xd.XDROP_E_INVALID
         res, _, _ = ctx.run(wl.records[:10])
         assert np.all(res["score"] > 0)
+
+
+def test_autotune_and_tuning_cache(xd, c0, tmp_path):
+    wl, ref = c0
+    note("autotune on c0 (sweep of launch parameters)")
+    cache = str(tmp_path / "tune.txt")
+    with xd.Context(wl.store) as ctx:
+        tuning, best_ms = ctx.autotune(wl.records, cache_path=cache)
+        assert best_ms > 0 and tuning["shrink_margin"] >= 1
+        res, cells, _ = ctx.run(wl.records, count_cells=True)
+    assert_same(res, cells, ref)
+    with xd.Context(wl.store, tuning_cache=cache) as ctx2:
+        assert ctx2.tuning() == tuning
+        # every setting gives the same results
+        ctx2.set_tuning(waves_per_cu=4, buckets=0, grow_margin=2, shrink_margin=1, generic_waves=8)
+        res2, cells2, _ = ctx2.run(wl.records, count_cells=True)
+    assert_same(res2, cells2, ref)

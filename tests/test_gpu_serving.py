@@ -1,0 +1,131 @@
+"""Serving loop on the GPU: many producer threads submit batches to one
+context; admitted batches run concurrently on their own streams (continuous
+batching).  Each batch's results must be identical alone and in the mix
+(integer path: tolerance 0), and admission must apply back-pressure when the
+HBM budget is exhausted.
+"""
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2309_07270_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(f"[gpu-serving] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def xd():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2309_07270_amd import xdrop
+    xdrop.load_library()
+    return xdrop
+
+
+@pytest.fixture(scope="module")
+def wl():
+    # c2-shaped reads (100x, mean 10 kb) on a smaller genome; X in {20,50,100}
+    return W.make_workload("c2", pairs=60000, genome=1_000_000)
+
+
+def test_alone_equals_mixed(xd, wl):
+    rng = np.random.default_rng(0)
+    n_prod, per = 25, 3
+    sizes = rng.integers(1000, 4000, size=n_prod * per)
+    starts = rng.integers(0, len(wl.records) - 4000, size=n_prod * per)
+    batches = [wl.records[s:s + z] for s, z in zip(starts, sizes)]
+    note(f"alone: {len(batches)} batches one at a time")
+    alone = []
+    with xd.Context(wl.store, max_inflight=1) as ctx:
+        for b in batches:
+            res, cells, _ = ctx.run(b, count_cells=True)
+            alone.append((res, cells))
+    note("mixed: 25 producer threads, 6 slots in flight")
+    mixed = [None] * len(batches)
+    errors = []
+    with xd.Context(wl.store, max_inflight=6) as ctx:
+        def producer(p):
+            try:
+                for k in range(per):
+                    i = p * per + k
+                    t, out, cells = ctx.submit(batches[i], count_cells=True)
+                    ctx.wait(t)
+                    mixed[i] = (out, cells)
+            except Exception as e:  # pragma: no cover - reported below
+                errors.append(e)
+        th = [threading.Thread(target=producer, args=(p,)) for p in range(n_prod)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join(timeout=120)
+    assert not errors, errors
+    for i, (a, m) in enumerate(zip(alone, mixed)):
+        assert m is not None, f"batch {i} missing"
+        assert np.array_equal(a[0], m[0]) and np.array_equal(a[1], m[1]), f"batch {i} differs"
+
+
+def test_admission_backpressure_and_timeouts(xd, wl):
+    recs = wl.records[:20000]
+    with xd.Context(wl.store) as probe:
+        one = probe.footprint(len(recs))
+        assert probe.footprint(60000) > 1.5 * one
+    note(f"HBM budget of 1.5 slots ({one * 1.5 / 2**20:.0f} MiB): one 20k batch fits, a second must wait")
+    with xd.Context(wl.store, max_inflight=4, hbm_budget_bytes=int(one * 1.5)) as ctx:
+        # the first batch (30k records, same slot size) keeps the GPU busy for tens of ms
+        t1, out1, _ = ctx.submit(wl.records[:30000])
+        with pytest.raises(xd.XdropError) as e:
+            ctx.submit(recs, admit_timeout_us=0)
+        assert e.value.status == xd.XDROP_E_BUSY
+        # a blocking submit is admitted once the first batch completes
+        t2, out2, _ = ctx.submit(recs, admit_timeout_us=-1)
+        ctx.wait(t1)
+        ctx.wait(t2)
+        assert np.array_equal(out1[:20000], out2)
+        # a batch that can never fit is refused outright
+        with pytest.raises(xd.XdropError) as e:
+            ctx.submit(wl.records[:60000])
+        assert e.value.status == xd.XDROP_E_NOMEM
+    note("wait(0) polls; unknown tickets are rejected; destroy drains")
+    with xd.Context(wl.store) as ctx:
+        t, out, _ = ctx.submit(wl.records[:30000])
+        try:
+            ctx.wait(t, timeout_us=0)
+        except xd.XdropError as e:
+            assert e.status == xd.XDROP_E_TIMEOUT
+            ctx.wait(t)
+        with pytest.raises(xd.XdropError) as e:
+            ctx.wait(t)
+        assert e.value.status == xd.XDROP_E_STATE
+        # destroy with an outstanding ticket: drains, then frees
+        ctx.submit(wl.records[:30000])
+    assert out["score"].min() > 0
+
+
+def test_overlap_on_device(xd, wl):
+    """Batches admitted together overlap on the GPU: four concurrent batches
+    finish in less wall time than four back to back."""
+    recs = wl.records[:15000]
+    with xd.Context(wl.store, max_inflight=4) as ctx:
+        for _ in range(2):  # warm-up: four slots with their graphs
+            ts = [ctx.submit(recs)[0] for _ in range(4)]
+            for t in ts:
+                ctx.wait(t)
+        t0 = time.perf_counter()
+        for _ in range(4):
+            ctx.run(recs)
+        serial = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ts = [ctx.submit(recs)[0] for _ in range(4)]
+        for t in ts:
+            ctx.wait(t)
+        overlapped = time.perf_counter() - t0
+    note(f"4 batches: serial {serial * 1e3:.1f} ms, overlapped {overlapped * 1e3:.1f} ms")
+    assert overlapped < serial
