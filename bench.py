@@ -121,6 +121,10 @@ def main():
     stream = torch.cuda.current_stream()
 
     ctx = X.Context(wl.store, mode=X.MODE_PERSISTENT)
+    # autotuner (untimed): launch parameters chosen on a 10,000-record sample
+    t0 = time.time()
+    tuning, tune_ms = ctx.autotune(recs[:10000])
+    log(f"autotune: {tuning} ({tune_ms:.2f} ms on the sample, {time.time() - t0:.1f}s)")
     # counting pass (untimed): exact candidate cells of every extension
     t = ctx.submit_device(d_recs, n, d_out, d_cells, stream=stream)
     ctx.wait(t)
@@ -157,6 +161,7 @@ def main():
     # stages (on the stream the kernels run on): per-kernel durations and the
     # cells each class completed
     pc = X.Context(wl.store, mode=X.MODE_PERSISTENT, profile=True)
+    pc.set_tuning(**tuning)
     pst = pc.wait(pc.submit_device(d_recs, n, d_out, d_cells, stream=stream))
     stage_cells, stage_tasks = pst["stage_cells"], pst["stage_tasks"]
     p_elapsed, p_lat, stage_ms = timed(pc, args.steps, 1)
@@ -188,6 +193,7 @@ def main():
                                   f"mean 8 kb sd 4 kb [1,30] kb, 15% error, k=17, X=50, +1/-1/-1"
                       if args.workload == "c1" else f"{args.workload}: {n} records",
                       "records": n, "cells_per_step": total_cells, "form": "persistent+hipGraph",
+                      "tuning": tuning,
                       "parallelism": "1 GPU"},
            "alignments_per_s": round(n * args.steps / elapsed, 1),
            "batched": {"gcups": round(gcups, 2), "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
@@ -204,6 +210,7 @@ def main():
 
     # plain form: the same records as sequential 10,000-record batches
     pctx = X.Context(wl.store, mode=X.MODE_PLAIN)
+    pctx.set_tuning(**tuning)
     chunk = 10000
     plat = []
     for _ in range(1):  # warm-up

@@ -170,9 +170,9 @@ xdrop_status xdrop_batch_wait(xdrop_ctx *c, xdrop_ticket t, int64_t timeout_us,
 xdrop_status xdrop_batch_destroy(xdrop_ctx *c);
 
 typedef struct {
-    int32_t grow_margin;          /* adaptive window: free slots per side after widening   */
+    int32_t grow_margin;          /* adaptive window: free slots per side after widening (>= 2) */
     int32_t shrink_margin;        /* adaptive window: narrow when the band fits C-1 cells
-                                     per lane with this many free slots per side (>= 1) */
+                                     per lane with this many free slots per side (>= 2) */
     int32_t waves_per_cu;         /* persistent grid: wavefronts per compute unit           */
     int32_t buckets;              /* 1: order extensions longest-first; 0: arrival order   */
     int32_t generic_waves;        /* grid of the unbounded-band kernel (multiple of 4)     */

@@ -45,7 +45,7 @@ using namespace xd;
 namespace {
 
 constexpr uint32_t kPlainChunk = 10000;
-constexpr uint64_t kGuardBases = 512;   // unused bases before and after the store
+constexpr uint64_t kGuardBases = 8192 + 64;   // unused bases before and after the store (kernel loads reach 8192 bases past a read)
 
 using clk = std::chrono::steady_clock;
 
@@ -599,8 +599,8 @@ bool ctx_idle(xdrop_ctx *c)
 
 void clamp_tuning(Tuning &t)
 {
-    t.grow_margin = std::min(std::max(t.grow_margin, 1), 64);
-    t.shrink_margin = std::min(std::max(t.shrink_margin, 1), 64);
+    t.grow_margin = std::min(std::max(t.grow_margin, 2), 64);
+    t.shrink_margin = std::min(std::max(t.shrink_margin, 2), 64);
     t.waves_per_cu = std::min(std::max(t.waves_per_cu, 1), 64);
     t.buckets = t.buckets ? 1 : 0;
     t.generic_waves = (std::min(std::max(t.generic_waves, 4), 4096) + 3) / 4 * 4;
@@ -706,7 +706,7 @@ xdrop_status xdrop_batch_create(const xdrop_config *cfg, xdrop_ctx **out)
         pos += ((uint64_t)L + 15) & ~uint64_t(15);
     }
     const uint64_t total_bases = pos + kGuardBases;
-    const uint64_t nwords = (total_bases + 15) / 16 + 4;
+    const uint64_t nwords = (total_bases + 15) / 16 + 16;
     std::vector<uint32_t> words(nwords, 0u);
     std::atomic<int64_t> bad{-1};
     {
@@ -883,7 +883,7 @@ xdrop_status xdrop_autotune(xdrop_ctx *c, const xdrop_record *recs, size_t n, co
     };
     std::vector<Tuning> grid;
     const int wpc[] = {8, 16, 24, 32};
-    const int margins[][2] = {{4, 2}, {8, 4}, {8, 6}, {12, 8}, {16, 12}};
+    const int margins[][2] = {{2, 2}, {4, 2}, {6, 3}, {8, 4}, {8, 6}, {12, 8}, {16, 12}};
     for (int w : wpc)
         for (int b = 0; b <= 1; ++b)
             for (auto &mg : margins) {

@@ -59,19 +59,24 @@ __device__ __forceinline__ uint32_t code_at(const uint32_t *__restrict__ W, uint
     return (W[p >> 4] >> ((p & 15) * 2)) & 3u;
 }
 
-// 16*NW codes starting at base p (clamped into the store): code t at bits
-// 2*(t & 15) of out[t >> 4].  Reads NW+1 words; the store keeps guard words
-// after its last base so that any clamped p stays inside it.
+// Guard of the store: reads keep at least kGuardWords words (8192 bases) before
+// their first and after their last base, so a lane's code window -- which
+// starts within 2 windows + 64 bases of its sequence -- never leaves the store.
+constexpr int kGuardWords = 512;
+
+// 16*NW codes starting at code p of a sequence whose first base sits at bit
+// 2*ph of word 0 of `seq` (seq = &store[first base / 16], ph = first base % 16):
+// code t at bits 2*(t & 15) of out[t >> 4].  Reads NW+1 words through a
+// wave-uniform base pointer and a 32-bit lane offset.
 template <int NW>
-__device__ __forceinline__ void load_codes(const uint32_t *__restrict__ W, int64_t p, int64_t maxp,
-                                           uint32_t (&out)[NW])
+__device__ __forceinline__ void load_codes(const uint32_t *__restrict__ seq, int ph, int p, uint32_t (&out)[NW])
 {
-    p = p < 0 ? 0 : (p > maxp ? maxp : p);
-    const uint64_t w = (uint64_t)p >> 4;
-    const uint32_t sh = (uint32_t)(p & 15) * 2u;
+    const int q = p + ph + 16 * kGuardWords;           // >= 0 for every window position
+    const uint32_t *w = seq - kGuardWords + (q >> 4);
+    const uint32_t sh = (uint32_t)(q & 15) * 2u;
     uint32_t raw[NW + 1];
 #pragma unroll
-    for (int i = 0; i <= NW; ++i) raw[i] = W[w + i];
+    for (int i = 0; i <= NW; ++i) raw[i] = w[i];
 #pragma unroll
     for (int i = 0; i < NW; ++i) out[i] = __builtin_amdgcn_alignbit(raw[i + 1], raw[i], sh);
 }
@@ -294,7 +299,11 @@ struct XState {
 constexpr int WMAX = 256;   // widest window of the adaptive kernel (C = 4): LDS slots per array
 enum : uint32_t { kDone = 0, kGrow = 1, kShrink = 2 };
 
-template <int C, bool COUNT, bool MA1, int STRIDE = WMAX>
+// Per-anti-diagonal sigma term.  SIGF: sigma - 2*gap of a match and of a
+// mismatch both lie in [0, 3]; each pair's value then sits in a 2-bit field
+// of a per-block word (one bfe + one add per cell).  Otherwise the diagonal
+// term is sm + bit * nd from the mismatch bit (bfe, mad, add).
+template <int C, bool COUNT, bool MA1, bool SIGF, int STRIDE = WMAX>
 struct Window {
     static constexpr int WIN = 64 * C;
     static constexpr int NWC = (C + UMAX + 16) / 16;   // words of codes per lane and block
@@ -302,7 +311,13 @@ struct Window {
 
     int Z1[C];                // anti-diagonal d-1 (Z units: S + |gap| * d; NEG = dead)
     int Z2[C];                // anti-diagonal d-2
-    uint32_t mmo[C], mme[C];  // mismatch bit (bit 2u) of pair u, odd / even anti-diagonal
+    uint32_t mmo[C], mme[C];  // per pair u: mismatch bit (bit 2u) or, SIGF, sigma field (bits 2u..2u+1)
+
+    // deferred end cell (MA1): last improving anti-diagonal of the block, its
+    // improvement mask over lanes and, per lane, the first improving slot r
+    int last_d;
+    uint64_t last_imp;
+    int last_r;
 
     // fresh extension: only (0,0) live, in the middle slot
     __device__ __forceinline__ void init(XState &s)
@@ -352,24 +367,30 @@ struct Window {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 
-    // One anti-diagonal d (ODD = d & 1).  thr_p / thr_i: drop and improvement
-    // thresholds of d in Z units (T_{d-1} - X and T_{d-1}, plus |gap| * d).
+    // One anti-diagonal d (ODD = d & 1).  tp / ti: drop and improvement
+    // thresholds of d in Z units (T_{d-1} - X and T_{d-1}, plus |gap| * d);
+    // on return they hold those of d+1.
     template <bool ODD, bool BOUNDS>
-    __device__ __forceinline__ void step(XState &s, int d, uint32_t ubit, int thr_p, int thr_i, int sm, int nd,
+    __device__ __forceinline__ void step(XState &s, int d, uint32_t ubit, int &tp, int &ti, int sm, int nd,
                                          int G, int m, int n)
     {
         const int lane = lane_id();
         int t[C];
+        // Gap predecessors come from the neighbouring slot of d-1, one lane
+        // over at the lane boundary.  A wave rotate (no invalid lanes) feeds
+        // it: the value wrapped into slot 0 / WIN-1 is that of the opposite
+        // edge slot, and the window keeps both edge slots out of every
+        // candidate range (see run), so the wrapped value is always dead.
         if (ODD) {
-            // gap predecessors: slots s-1 and s of d-1 (wave_shr: lane l reads lane l-1)
-            t[0] = max(__builtin_amdgcn_update_dpp((int)0x80000000, Z1[C - 1], 0x138, 0xf, 0xf, false), Z1[0]);
+            // slots s-1 and s (wave_ror: lane l reads lane l-1, lane 0 reads lane 63)
+            t[0] = max(__builtin_amdgcn_mov_dpp(Z1[C - 1], 0x13C, 0xf, 0xf, true), Z1[0]);
 #pragma unroll
             for (int r = 1; r < C; ++r) t[r] = max(Z1[r - 1], Z1[r]);
         } else {
-            // gap predecessors: slots s and s+1 of d-1 (wave_shl: lane l reads lane l+1)
+            // slots s and s+1 (wave_rol: lane l reads lane l+1, lane 63 reads lane 0)
 #pragma unroll
             for (int r = 0; r < C - 1; ++r) t[r] = max(Z1[r], Z1[r + 1]);
-            t[C - 1] = max(__builtin_amdgcn_update_dpp((int)0x80000000, Z1[0], 0x130, 0xf, 0xf, false), Z1[C - 1]);
+            t[C - 1] = max(__builtin_amdgcn_mov_dpp(Z1[0], 0x134, 0xf, 0xf, true), Z1[C - 1]);
         }
         int lo_s = 0, hi_s = 0;
         if (BOUNDS) {
@@ -381,28 +402,49 @@ struct Window {
         int v[C];
 #pragma unroll
         for (int r = 0; r < C; ++r) {
-            const uint32_t mm = ODD ? mmo[r] : mme[r];
-            const int bit = (int)__builtin_amdgcn_ubfe(mm, ubit, 1u);
-            const int sig = __mul24(bit, nd) + sm;          // sigma - 2*gap
+            const uint32_t w = ODD ? mmo[r] : mme[r];
+            int sig;
+            if (SIGF) {
+                sig = (int)__builtin_amdgcn_ubfe(w, ubit, 2u);
+            } else {
+                const int bit = (int)__builtin_amdgcn_ubfe(w, ubit, 1u);
+                sig = __mul24(bit, nd) + sm;          // sigma - 2*gap
+            }
             v[r] = max(t[r], Z2[r] + sig);
             const int sl = C * lane + r;
             const bool inb = !BOUNDS || (sl >= lo_s && sl <= hi_s);
-            imp |= ballot(inb && v[r] > thr_i);
+            imp |= ballot(inb && v[r] > ti);
             if (COUNT) s.cells += (uint64_t)__builtin_popcountll(ballot(inb && v[r] > NEG_HALF));
-            t[r] = (inb && v[r] >= thr_p) ? v[r] : NEG;
+            t[r] = (inb && v[r] >= tp) ? v[r] : NEG;
         }
-        if (imp) {
-            int vmax = thr_i + 1;   // match weight 1: any improving cell holds exactly T + 1
-            if (!MA1) {
-                int lm = NEG;
+        if (MA1) {
+            // match weight 1: an improving cell holds exactly T_{d-1} + 1; the
+            // end cell is resolved once per block from the last improvement
+            if (imp) {
+                last_d = d;
+                last_imp = imp;
+                if (C > 1) {
+                    int rl = C - 1;
 #pragma unroll
-                for (int r = 0; r < C; ++r) {
-                    const int sl = C * lane + r;
-                    const bool inb = !BOUNDS || (sl >= lo_s && sl <= hi_s);
-                    lm = max(lm, inb ? v[r] : NEG);
+                    for (int r = C - 1; r >= 0; --r) {
+                        const int sl = C * lane + r;
+                        const bool inb = !BOUNDS || (sl >= lo_s && sl <= hi_s);
+                        if (inb && v[r] > ti) rl = r;
+                    }
+                    last_r = rl;
                 }
-                vmax = uni(wave_max(lm));
+                ++tp;
+                ++ti;
             }
+        } else if (imp) {
+            int lm = NEG;
+#pragma unroll
+            for (int r = 0; r < C; ++r) {
+                const int sl = C * lane + r;
+                const bool inb = !BOUNDS || (sl >= lo_s && sl <= hi_s);
+                lm = max(lm, inb ? v[r] : NEG);
+            }
+            const int vmax = uni(wave_max(lm));
             // first slot (smallest lane, then smallest r) holding vmax
             int rl = C;
 #pragma unroll
@@ -414,15 +456,29 @@ struct Window {
             const uint64_t any = ballot(rl < C);
             const int l = __builtin_ctzll(any);
             const int rr = __builtin_amdgcn_readlane(rl, l);
-            s.T = vmax - G * d;
             s.bi = s.base + (d >> 1) + C * l + rr;
             s.bj = d - s.bi;
+            tp += vmax - ti;
+            ti = vmax;
         }
+        tp += G;
+        ti += G;
 #pragma unroll
         for (int r = 0; r < C; ++r) {
             Z2[r] = Z1[r];
             Z1[r] = t[r];
         }
+    }
+
+    // end cell of the last improvement recorded in this block (MA1)
+    __device__ __forceinline__ void resolve(XState &s)
+    {
+        if (!MA1 || last_d < 0) return;
+        const int l = __builtin_ctzll(last_imp);
+        const int rr = C > 1 ? __builtin_amdgcn_readlane(last_r, l) : 0;
+        s.bi = s.base + (last_d >> 1) + C * l + rr;
+        s.bj = last_d - s.bi;
+        last_d = -1;
     }
 
     // live slots over the last two anti-diagonals; false when both are dead
@@ -450,70 +506,102 @@ struct Window {
         const int m = g.m, n = g.n;
         const int G = -gap;
         const int sm = ma + 2 * G;          // sigma(match) - 2*gap
+        const int sx = mi + 2 * G;          // sigma(mismatch) - 2*gap
         const int nd = mi - ma;             // mismatch - match
         const int dend = m + n;
+        const uint32_t *aseq = W + (g.abase >> 4), *bseq = W + (g.bbase >> 4);
+        const int aph = (int)(g.abase & 15), bph = (int)(g.bbase & 15);
+        (void)maxp;
+        last_d = -1;
         while (s.d <= dend) {
             int mn, mx;
             if (!band(mn, mx)) break;                 // two dead anti-diagonals
+            // Over a block of U pairs the candidate slots stay inside
+            // [mn - U, mx + U]; they must also avoid the two edge slots.
             const int width = mx - mn + 1;
-            if (width + 2 > WIN || width <= shrink_width) {
+            if (width + 4 > WIN || width <= shrink_width) {
                 save(lds);
                 s.mn = mn;
                 s.mx = mx;
-                return width + 2 > WIN ? kGrow : kShrink;
+                return width + 4 > WIN ? kGrow : kShrink;
             }
             const int d = s.d;
-            int U = min(UMAX, (WIN - width) / 2);
-            U = min(U, (dend - d + 2) >> 1);
-            if (mn < U || mx > WIN - 1 - U) {
+            const int upairs = (dend - d + 2) >> 1;           // pairs left to the far corner
+            // block length without moving the window, and after re-centring;
+            // re-centre only when that gains more than two pairs
+            const int u_here = min(mn - 1, WIN - 2 - mx);
+            const int u_centred = (WIN - 2 - width) / 2;
+            int U;
+            if (u_here >= 1 && (u_here >= UMAX || u_here >= upairs || u_here + 2 >= u_centred)) {
+                U = min(min(UMAX, u_here), upairs);
+            } else {
                 const int delta = mn - (WIN - width) / 2;
                 save(lds);
                 load(lds, WIN, delta);
                 s.base += delta;
+                U = min(min(UMAX, u_centred), upairs);
             }
             // codes for this block: slot r of this lane meets a[A0 + C*lane + r + u
             // (+1 on even d)] and b[B0 - C*lane - r + u] at pair u
             const int e0 = (d - 1) >> 1;
-            const int64_t A0 = (int64_t)s.base + e0 - 1;
-            const int64_t B0 = (int64_t)e0 - s.base;
+            const int A0 = s.base + e0 - 1;
+            const int B0 = e0 - s.base;
             uint32_t aw[NWC], bw[NWC];
-            load_codes<NWC>(W, (int64_t)g.abase + A0 + C * lane, maxp, aw);
-            load_codes<NWC>(W, (int64_t)g.bbase + B0 - C * lane - (C - 1), maxp, bw);
+            load_codes<NWC>(aseq, aph, A0 + C * lane, aw);
+            load_codes<NWC>(bseq, bph, B0 - C * lane - (C - 1), bw);
 #pragma unroll
             for (int r = 0; r < C; ++r) {
                 const uint32_t bb = codes16<NWC>(bw, C - 1 - r);
                 const uint32_t xo = codes16<NWC>(aw, r) ^ bb;
                 const uint32_t xe = codes16<NWC>(aw, r + 1) ^ bb;
-                mmo[r] = (xo | (xo >> 1)) & 0x55555555u;
-                mme[r] = (xe | (xe >> 1)) & 0x55555555u;
+                const uint32_t mo = (xo | (xo >> 1)) & 0x55555555u;   // 1 = mismatch, at bit 2u
+                const uint32_t me = (xe | (xe >> 1)) & 0x55555555u;
+                if (SIGF) {
+                    // field u = sigma'' of pair u: sm ^ (mismatch ? sm ^ sx : 0)
+                    const uint32_t base_f = (uint32_t)sm * 0x55555555u;
+                    const uint32_t k = (uint32_t)(sm ^ sx);
+                    mmo[r] = base_f ^ ((k & 1u) ? mo : 0u) ^ ((k & 2u) ? (mo << 1) : 0u);
+                    mme[r] = base_f ^ ((k & 1u) ? me : 0u) ^ ((k & 2u) ? (me << 1) : 0u);
+                } else {
+                    mmo[r] = mo;
+                    mme[r] = me;
+                }
             }
+            int tp = s.T - X + G * d, ti = s.T + G * d;
             const int dlast = d + 2 * U - 1;
             const int o_first = s.base + (d >> 1), o_last = s.base + (dlast >> 1);
             const bool fast = o_first >= 0 && o_last >= dlast - n && o_last + WIN - 1 <= m &&
                               o_first + WIN - 1 <= d;
             if (fast) {
                 for (int u = 0; u < U; ++u) {
-                    const int dd = d + 2 * u;
                     const uint32_t ub = 2u * (uint32_t)u;
-                    step<true, false>(s, dd, ub, s.T - X + G * dd, s.T + G * dd, sm, nd, G, m, n);
-                    step<false, false>(s, dd + 1, ub, s.T - X + G * (dd + 1), s.T + G * (dd + 1), sm, nd, G, m, n);
+                    step<true, false>(s, d + 2 * u, ub, tp, ti, sm, nd, G, m, n);
+                    step<false, false>(s, d + 2 * u + 1, ub, tp, ti, sm, nd, G, m, n);
                 }
             } else {
                 for (int u = 0; u < U; ++u) {
-                    const int dd = d + 2 * u;
                     const uint32_t ub = 2u * (uint32_t)u;
-                    step<true, true>(s, dd, ub, s.T - X + G * dd, s.T + G * dd, sm, nd, G, m, n);
-                    step<false, true>(s, dd + 1, ub, s.T - X + G * (dd + 1), s.T + G * (dd + 1), sm, nd, G, m, n);
+                    step<true, true>(s, d + 2 * u, ub, tp, ti, sm, nd, G, m, n);
+                    step<false, true>(s, d + 2 * u + 1, ub, tp, ti, sm, nd, G, m, n);
                 }
             }
             s.d = d + 2 * U;
+            s.T = ti - G * s.d;
+            resolve(s);
         }
         return kDone;
     }
 };
 
-template <int C, bool COUNT, bool MA1>
-using WideWindow = Window<C, COUNT, MA1, 64 * C>;
+template <int C, bool COUNT, bool MA1, bool SIGF>
+using WideWindow = Window<C, COUNT, MA1, SIGF, 64 * C>;
+
+// sigma - 2*gap of a match and of a mismatch both in [0, 3]
+__device__ __forceinline__ bool sigma_fits_2bits(const Task &k)
+{
+    const int sm = k.ma - 2 * k.gap, sx = k.mi - 2 * k.gap;
+    return sm >= 0 && sm <= 3 && sx >= 0 && sx <= 3;
+}
 
 // Smallest adaptive width (cells per lane) whose window holds `width` live
 // slots with `margin` slots of slack on each side; 0 if none does.
@@ -524,19 +612,21 @@ __device__ __forceinline__ int fit_c(int width, int margin)
         if (width + 2 * margin <= 64 * c) return c;
     return 0;
 }
+// (a window must hold the band plus one block pair and one edge slot per side)
 
 // One extension with a window that widens and narrows with its band:
 // C = 1..4 cells per lane, the live band handed over through LDS.  Returns
 // false if the band outgrew the widest window (the task then restarts in the
 // next class).
-template <bool COUNT, bool MA1>
+template <bool COUNT, bool MA1, bool SIGF>
 __device__ bool run_adaptive(const uint32_t *__restrict__ W, int64_t maxp, const Task &k, int *lds, XState &s,
                              int grow_margin, int shrink_margin)
 {
-    // margins >= 1: a band that was just narrowed fits its new window with a
-    // free slot on each side, so it cannot be widened again before a block runs
-    grow_margin = max(grow_margin, 1);
-    shrink_margin = max(shrink_margin, 1);
+    // margins >= 2: a band that was just narrowed fits its new window with
+    // two free slots per side (an edge slot plus one pair), so it cannot be
+    // widened again before a block runs
+    grow_margin = max(grow_margin, 2);
+    shrink_margin = max(shrink_margin, 2);
     int C = 1, from_win = 0, delta = 0;
     bool fresh = true;
     for (;;) {
@@ -545,22 +635,22 @@ __device__ bool run_adaptive(const uint32_t *__restrict__ W, int64_t maxp, const
         uint32_t st;
         switch (C) {
         case 1: {
-            Window<1, COUNT, MA1> w;
+            Window<1, COUNT, MA1, SIGF> w;
             if (fresh) w.init(s); else w.load(lds, from_win, delta);
             st = w.run(W, maxp, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
         } break;
         case 2: {
-            Window<2, COUNT, MA1> w;
+            Window<2, COUNT, MA1, SIGF> w;
             if (fresh) w.init(s); else w.load(lds, from_win, delta);
             st = w.run(W, maxp, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
         } break;
         case 3: {
-            Window<3, COUNT, MA1> w;
+            Window<3, COUNT, MA1, SIGF> w;
             if (fresh) w.init(s); else w.load(lds, from_win, delta);
             st = w.run(W, maxp, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
         } break;
         default: {
-            Window<4, COUNT, MA1> w;
+            Window<4, COUNT, MA1, SIGF> w;
             if (fresh) w.init(s); else w.load(lds, from_win, delta);
             st = w.run(W, maxp, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
         } break;
@@ -571,7 +661,7 @@ __device__ bool run_adaptive(const uint32_t *__restrict__ W, int64_t maxp, const
         int nc;
         if (st == kGrow) {
             nc = fit_c(width, grow_margin);
-            if (nc == 0) nc = fit_c(width, 1);
+            if (nc == 0) nc = fit_c(width, 2);
             if (nc == 0) return false;
         } else {
             nc = C - 1;
@@ -598,8 +688,13 @@ __global__ void __launch_bounds__(256) adaptive_kernel(BatchDev b, StoreDev st, 
         const uint32_t t = (uint32_t)uni((int)b.qbuf[cls * qcap + idx]);
         const Task k = load_task(b.recs, st.reads, t);
         XState s;
-        const bool ok = k.ma == 1 ? run_adaptive<COUNT, true>(st.words, st.max_base, k, lds, s, grow_margin, shrink_margin)
-                                  : run_adaptive<COUNT, false>(st.words, st.max_base, k, lds, s, grow_margin, shrink_margin);
+        bool ok;
+        if (k.ma != 1)
+            ok = run_adaptive<COUNT, false, false>(st.words, st.max_base, k, lds, s, grow_margin, shrink_margin);
+        else if (sigma_fits_2bits(k))
+            ok = run_adaptive<COUNT, true, true>(st.words, st.max_base, k, lds, s, grow_margin, shrink_margin);
+        else
+            ok = run_adaptive<COUNT, true, false>(st.words, st.max_base, k, lds, s, grow_margin, shrink_margin);
         if (ok) {
             TaskOut o;   // every lane stores the same (wave-uniform) values
             o.score = s.T; o.i = s.bi; o.j = s.bj; o.status = (uint32_t)cls; o.cells = s.cells;
@@ -626,12 +721,16 @@ __global__ void __launch_bounds__(256) wide_kernel(BatchDev b, StoreDev st, int 
         const Task k = load_task(b.recs, st.reads, t);
         XState s;
         uint32_t status;
-        if (k.ma == 1) {
-            WideWindow<C, COUNT, true> w;
+        if (k.ma != 1) {
+            WideWindow<C, COUNT, false, false> w;
+            w.init(s);
+            status = w.run(st.words, st.max_base, k.g, k.x, k.ma, k.mi, k.gap, lds, s, -1);
+        } else if (sigma_fits_2bits(k)) {
+            WideWindow<C, COUNT, true, true> w;
             w.init(s);
             status = w.run(st.words, st.max_base, k.g, k.x, k.ma, k.mi, k.gap, lds, s, -1);
         } else {
-            WideWindow<C, COUNT, false> w;
+            WideWindow<C, COUNT, true, false> w;
             w.init(s);
             status = w.run(st.words, st.max_base, k.g, k.x, k.ma, k.mi, k.gap, lds, s, -1);
         }

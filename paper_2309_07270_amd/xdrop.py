@@ -139,11 +139,16 @@ class Context:
             raise XdropError(st, self.lib.xdrop_last_error(None).decode())
         self.h = h
         self.n_reads = len(seqs)
+        # output buffers of outstanding tickets: the library writes them when a
+        # batch completes, so they are kept alive until wait() consumes the
+        # ticket or close() has drained every batch
+        self._pending = {}
 
     def close(self):
         if getattr(self, "h", None):
             self.lib.xdrop_batch_destroy(self.h)
             self.h = None
+            self._pending.clear()
 
     def __enter__(self):
         return self
@@ -199,11 +204,14 @@ class Context:
                                          _ptr(cells) if (cells is not None and n) else None,
                                          admit_timeout_us, ctypes.byref(t))
         self._check(st)
+        self._pending[t.value] = (out, cells)
         return t.value, out, cells
 
     def wait(self, ticket: int, timeout_us: int = -1) -> dict:
         s = Stats()
         st = self.lib.xdrop_batch_wait(self.h, ticket, timeout_us, ctypes.byref(s))
+        if st != XDROP_E_TIMEOUT:   # the ticket is consumed (done or failed)
+            self._pending.pop(ticket, None)
         self._check(st)
         return s.as_dict()
 
@@ -221,6 +229,7 @@ class Context:
                                                 _ptr(d_cells) if d_cells is not None else None, sp,
                                                 ctypes.byref(t))
         self._check(st)
+        self._pending[t.value] = (d_recs, d_out, d_cells)
         return t.value
 
 

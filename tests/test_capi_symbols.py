@@ -64,3 +64,11 @@ def test_create_rejects_bad_reads_before_touching_the_device():
         h = ctypes.c_void_p()
         assert lib.xdrop_batch_create(ctypes.byref(cfg), ctypes.byref(h)) == X.XDROP_E_INVALID
         assert not h.value
+
+
+def test_binding_keeps_output_buffers_alive_until_wait():
+    """The library writes results when a batch completes: the binding must hold
+    the output arrays of an outstanding ticket even if the caller drops them."""
+    import inspect
+    src = inspect.getsource(X.Context)
+    assert "_pending[t.value]" in src and "_pending.pop(ticket" in src

@@ -74,9 +74,10 @@ def test_alone_equals_mixed(xd, wl):
 
 def test_admission_backpressure_and_timeouts(xd, wl):
     recs = wl.records[:20000]
+    big = np.tile(wl.records, 20)[:1 << 20]
     with xd.Context(wl.store) as probe:
         one = probe.footprint(len(recs))
-        assert probe.footprint(60000) > 1.5 * one
+        assert probe.footprint(len(big)) > 1.5 * one
     note(f"HBM budget of 1.5 slots ({one * 1.5 / 2**20:.0f} MiB): one 20k batch fits, a second must wait")
     with xd.Context(wl.store, max_inflight=4, hbm_budget_bytes=int(one * 1.5)) as ctx:
         # the first batch (30k records, same slot size) keeps the GPU busy for tens of ms
@@ -91,7 +92,7 @@ def test_admission_backpressure_and_timeouts(xd, wl):
         assert np.array_equal(out1[:20000], out2)
         # a batch that can never fit is refused outright
         with pytest.raises(xd.XdropError) as e:
-            ctx.submit(wl.records[:60000])
+            ctx.submit(big)
         assert e.value.status == xd.XDROP_E_NOMEM
     note("wait(0) polls; unknown tickets are rejected; destroy drains")
     with xd.Context(wl.store) as ctx:
