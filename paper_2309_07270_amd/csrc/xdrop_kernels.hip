@@ -37,6 +37,7 @@ namespace {
 constexpr int NEG = -(1 << 30) - (1 << 20);   // dead / outside the table
 constexpr int NEG_HALF = -(1 << 29);          // anything below is "no live predecessor"
 constexpr int UMAX = 16;                      // anti-diagonal pairs per block (max)
+constexpr int kRecentre = 4;                  // a block starting nearer an edge re-centres the band
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
@@ -318,6 +319,10 @@ struct Window {
     int last_d;
     uint64_t last_imp;
     int last_r;
+    // C = 1: the same per parity of d (odd / even step of a pair), as the
+    // pair offset 2u of the step (-1: none in this block)
+    int lu_o, lu_e;
+    uint64_t li_o, li_e;
 
     // fresh extension: only (0,0) live, in the middle slot
     __device__ __forceinline__ void init(XState &s)
@@ -367,20 +372,21 @@ struct Window {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 
-    // One anti-diagonal d (ODD = d & 1).  tp / ti: drop and improvement
-    // thresholds of d in Z units (T_{d-1} - X and T_{d-1}, plus |gap| * d);
-    // on return they hold those of d+1.
+    // One anti-diagonal d (ODD = d & 1) at pair offset ub = 2u of the block.
+    // tp / ti: drop and improvement thresholds of d in Z units (T_{d-1} - X
+    // and T_{d-1}, plus |gap| * d); on return they hold those of d+1.  Returns
+    // the live cells of d in the two edge slots on either side of the window
+    // (bit per lane).
     template <bool ODD, bool BOUNDS>
-    __device__ __forceinline__ void step(XState &s, int d, uint32_t ubit, int &tp, int &ti, int sm, int nd,
-                                         int G, int m, int n)
+    __device__ __forceinline__ uint64_t step(XState &s, int d, uint32_t ub, int &tp, int &ti, int sm, int nd,
+                                             int G, int X, int m, int n)
     {
         const int lane = lane_id();
         int t[C];
         // Gap predecessors come from the neighbouring slot of d-1, one lane
         // over at the lane boundary.  A wave rotate (no invalid lanes) feeds
         // it: the value wrapped into slot 0 / WIN-1 is that of the opposite
-        // edge slot, and the window keeps both edge slots out of every
-        // candidate range (see run), so the wrapped value is always dead.
+        // edge slot, which run() keeps dead.
         if (ODD) {
             // slots s-1 and s (wave_ror: lane l reads lane l-1, lane 0 reads lane 63)
             t[0] = max(__builtin_amdgcn_mov_dpp(Z1[C - 1], 0x13C, 0xf, 0xf, true), Z1[0]);
@@ -398,87 +404,137 @@ struct Window {
             lo_s = max(0, d - n) - o;
             hi_s = min(m, d) - o;
         }
-        uint64_t imp = 0;
+        uint64_t imp = 0, lm[C];
         int v[C];
 #pragma unroll
         for (int r = 0; r < C; ++r) {
             const uint32_t w = ODD ? mmo[r] : mme[r];
             int sig;
             if (SIGF) {
-                sig = (int)__builtin_amdgcn_ubfe(w, ubit, 2u);
+                sig = (int)__builtin_amdgcn_ubfe(w, ub, 2u);
             } else {
-                const int bit = (int)__builtin_amdgcn_ubfe(w, ubit, 1u);
+                const int bit = (int)__builtin_amdgcn_ubfe(w, ub, 1u);
                 sig = __mul24(bit, nd) + sm;          // sigma - 2*gap
             }
             v[r] = max(t[r], Z2[r] + sig);
+            // lane masks from single compares (a ballot of a compound
+            // condition costs two extra vector ops)
             const int sl = C * lane + r;
-            const bool inb = !BOUNDS || (sl >= lo_s && sl <= hi_s);
-            imp |= ballot(inb && v[r] > ti);
-            if (COUNT) s.cells += (uint64_t)__builtin_popcountll(ballot(inb && v[r] > NEG_HALF));
-            t[r] = (inb && v[r] >= tp) ? v[r] : NEG;
+            const uint64_t inbm = BOUNDS ? ballot(sl >= lo_s) & ballot(sl <= hi_s) : ~0ull;
+            imp |= ballot(v[r] > ti) & inbm;
+            if (COUNT) s.cells += (uint64_t)__builtin_popcountll(ballot(v[r] > NEG_HALF) & inbm);
+            lm[r] = ballot(v[r] >= tp) & inbm;
+            const bool keep = BOUNDS ? (sl >= lo_s && sl <= hi_s && v[r] >= tp) : v[r] >= tp;
+            t[r] = keep ? v[r] : NEG;
         }
-        if (MA1) {
-            // match weight 1: an improving cell holds exactly T_{d-1} + 1; the
-            // end cell is resolved once per block from the last improvement
+        if (MA1 && C == 1) {
+            // match weight 1: an improving cell holds exactly T_{d-1} + 1.
+            // Keep the last improvement mask and pair offset of this parity,
+            // then ti += G + (imp != 0) and tp = ti - X, all on the scalar
+            // unit without a branch.
+            uint64_t &li = ODD ? li_o : li_e;
+            int &lu = ODD ? lu_o : lu_e;
+            asm volatile("s_cmp_lg_u64 %[imp], 0\n\t"
+                         "s_cselect_b64 %[li], %[imp], %[li]\n\t"
+                         "s_cselect_b32 %[lu], %[ub], %[lu]\n\t"
+                         "s_addc_u32 %[ti], %[ti], %[g]\n\t"
+                         "s_sub_i32 %[tp], %[ti], %[x]"
+                         : [li] "+s"(li), [lu] "+s"(lu), [ti] "+s"(ti), [tp] "=s"(tp)
+                         : [imp] "s"(imp), [ub] "s"(ub), [g] "s"(G), [x] "s"(X)
+                         : "scc");
+        } else if (MA1) {
             if (imp) {
                 last_d = d;
                 last_imp = imp;
-                if (C > 1) {
-                    int rl = C - 1;
+                int rl = C - 1;
 #pragma unroll
-                    for (int r = C - 1; r >= 0; --r) {
-                        const int sl = C * lane + r;
-                        const bool inb = !BOUNDS || (sl >= lo_s && sl <= hi_s);
-                        if (inb && v[r] > ti) rl = r;
-                    }
-                    last_r = rl;
+                for (int r = C - 1; r >= 0; --r) {
+                    const int sl = C * lane + r;
+                    const bool inb = !BOUNDS || (sl >= lo_s && sl <= hi_s);
+                    if (inb && v[r] > ti) rl = r;
                 }
+                last_r = rl;
                 ++tp;
                 ++ti;
             }
-        } else if (imp) {
-            int lm = NEG;
+            tp += G;
+            ti += G;
+        } else {
+            if (imp) {
+                int lm_ = NEG;
 #pragma unroll
-            for (int r = 0; r < C; ++r) {
-                const int sl = C * lane + r;
-                const bool inb = !BOUNDS || (sl >= lo_s && sl <= hi_s);
-                lm = max(lm, inb ? v[r] : NEG);
-            }
-            const int vmax = uni(wave_max(lm));
-            // first slot (smallest lane, then smallest r) holding vmax
-            int rl = C;
+                for (int r = 0; r < C; ++r) {
+                    const int sl = C * lane + r;
+                    const bool inb = !BOUNDS || (sl >= lo_s && sl <= hi_s);
+                    lm_ = max(lm_, inb ? v[r] : NEG);
+                }
+                const int vmax = uni(wave_max(lm_));
+                // first slot (smallest lane, then smallest r) holding vmax
+                int rl = C;
 #pragma unroll
-            for (int r = C - 1; r >= 0; --r) {
-                const int sl = C * lane + r;
-                const bool inb = !BOUNDS || (sl >= lo_s && sl <= hi_s);
-                if (inb && v[r] == vmax) rl = r;
+                for (int r = C - 1; r >= 0; --r) {
+                    const int sl = C * lane + r;
+                    const bool inb = !BOUNDS || (sl >= lo_s && sl <= hi_s);
+                    if (inb && v[r] == vmax) rl = r;
+                }
+                const uint64_t any = ballot(rl < C);
+                const int l = __builtin_ctzll(any);
+                const int rr = __builtin_amdgcn_readlane(rl, l);
+                s.bi = s.base + (d >> 1) + C * l + rr;
+                s.bj = d - s.bi;
+                tp += vmax - ti;
+                ti = vmax;
             }
-            const uint64_t any = ballot(rl < C);
-            const int l = __builtin_ctzll(any);
-            const int rr = __builtin_amdgcn_readlane(rl, l);
-            s.bi = s.base + (d >> 1) + C * l + rr;
-            s.bj = d - s.bi;
-            tp += vmax - ti;
-            ti = vmax;
+            tp += G;
+            ti += G;
         }
-        tp += G;
-        ti += G;
 #pragma unroll
         for (int r = 0; r < C; ++r) {
             Z2[r] = Z1[r];
             Z1[r] = t[r];
         }
+        // slots 0, 1 (lane 0 unless C = 1) and WIN-2, WIN-1 (lane 63 unless C = 1)
+        if (C == 1) return lm[0];   // next_pair masks lanes 0, 1, 62, 63
+        return ((lm[0] | lm[1]) & 1ull) | ((lm[C - 2] | lm[C - 1]) & (1ull << 63));
     }
 
-    // end cell of the last improvement recorded in this block (MA1)
-    __device__ __forceinline__ void resolve(XState &s)
+    // end cell of the last improvement recorded in the block that began at d0
+    // (MA1): the later of the last odd and the last even improving step
+    __device__ __forceinline__ void resolve(XState &s, int d0)
     {
-        if (!MA1 || last_d < 0) return;
+        if (!MA1) return;
+        if (C == 1) {
+            if ((lu_o & lu_e) < 0) return;                 // both -1: none
+            const bool ev = lu_e >= lu_o;
+            const uint64_t im = ev ? li_e : li_o;
+            const int dd = d0 + (ev ? lu_e + 1 : lu_o);
+            s.bi = s.base + (dd >> 1) + __builtin_ctzll(im);
+            s.bj = dd - s.bi;
+            lu_o = lu_e = -1;
+            return;
+        }
+        if (last_d < 0) return;
         const int l = __builtin_ctzll(last_imp);
-        const int rr = C > 1 ? __builtin_amdgcn_readlane(last_r, l) : 0;
+        const int rr = __builtin_amdgcn_readlane(last_r, l);
         s.bi = s.base + (last_d >> 1) + C * l + rr;
         s.bj = last_d - s.bi;
         last_d = -1;
+    }
+
+    // ub + 2, plus 64 when e has a live edge cell: s_and_b64 sets SCC, a
+    // select and one add (a second loop exit would cost a chain of selects)
+    __device__ __forceinline__ static uint32_t next_pair(uint32_t ub, uint64_t e)
+    {
+        const uint64_t edge = C == 1 ? 0xC000000000000003ull : ~0ull;
+        uint64_t tmp;
+        uint32_t inc;
+        asm volatile("s_and_b64 %[tmp], %[e], %[edge]\n\t"
+                     "s_cselect_b32 %[inc], 66, 2\n\t"
+                     "s_add_u32 %[ub], %[ub], %[inc]"
+                     : [tmp] "=&s"(tmp), [inc] "=&s"(inc), [ub] "+s"(ub)
+                     : [e] "s"(e), [edge] "s"(edge)
+                     : "scc");
+        return ub;
     }
 
     // live slots over the last two anti-diagonals; false when both are dead
@@ -499,6 +555,16 @@ struct Window {
 
     // Advance the extension block by block.  Returns kDone, or kGrow / kShrink
     // with the window saved to LDS and s.mn / s.mx set (shrink_width < 0: never).
+    //
+    // A block covers up to UMAX anti-diagonal pairs (odd d, even d+1) with one
+    // load of codes.  The odd step of a pair can add a candidate one slot to
+    // the right of the band, the even step one slot to the left.  A block
+    // starts with the live band of the last two anti-diagonals inside
+    // [2, WIN-3] and ends after the first pair whose even anti-diagonal has a
+    // live cell in slot 0, 1, WIN-2 or WIN-1.  Before every pair the even
+    // anti-diagonal is then live inside [2, WIN-3] and the odd one inside
+    // [1, WIN-2]: every candidate lies in the window and the value a rotate
+    // wraps around from the far edge slot is dead.
     __device__ uint32_t run(const uint32_t *__restrict__ W, int64_t maxp, const Geo &g, int X, int ma, int mi,
                             int gap, int *lds, XState &s, int shrink_width)
     {
@@ -513,11 +579,11 @@ struct Window {
         const int aph = (int)(g.abase & 15), bph = (int)(g.bbase & 15);
         (void)maxp;
         last_d = -1;
+        lu_o = lu_e = -1;
+        li_o = li_e = 0;
         while (s.d <= dend) {
             int mn, mx;
             if (!band(mn, mx)) break;                 // two dead anti-diagonals
-            // Over a block of U pairs the candidate slots stay inside
-            // [mn - U, mx + U]; they must also avoid the two edge slots.
             const int width = mx - mn + 1;
             if (width + 4 > WIN || width <= shrink_width) {
                 save(lds);
@@ -525,22 +591,15 @@ struct Window {
                 s.mx = mx;
                 return width + 4 > WIN ? kGrow : kShrink;
             }
-            const int d = s.d;
-            const int upairs = (dend - d + 2) >> 1;           // pairs left to the far corner
-            // block length without moving the window, and after re-centring;
-            // re-centre only when that gains more than two pairs
-            const int u_here = min(mn - 1, WIN - 2 - mx);
-            const int u_centred = (WIN - 2 - width) / 2;
-            int U;
-            if (u_here >= 1 && (u_here >= UMAX || u_here >= upairs || u_here + 2 >= u_centred)) {
-                U = min(min(UMAX, u_here), upairs);
-            } else {
+            // re-centre the band when it starts closer than kRecentre slots to an edge
+            if (min(mn, WIN - 1 - mx) < kRecentre) {
                 const int delta = mn - (WIN - width) / 2;
                 save(lds);
                 load(lds, WIN, delta);
                 s.base += delta;
-                U = min(min(UMAX, u_centred), upairs);
             }
+            const int d = s.d;
+            const int P = min(UMAX, (dend - d + 2) >> 1);   // pairs up to the far corner
             // codes for this block: slot r of this lane meets a[A0 + C*lane + r + u
             // (+1 on even d)] and b[B0 - C*lane - r + u] at pair u
             const int e0 = (d - 1) >> 1;
@@ -568,26 +627,35 @@ struct Window {
                 }
             }
             int tp = s.T - X + G * d, ti = s.T + G * d;
-            const int dlast = d + 2 * U - 1;
+            const int dlast = d + 2 * P - 1;
             const int o_first = s.base + (d >> 1), o_last = s.base + (dlast >> 1);
             const bool fast = o_first >= 0 && o_last >= dlast - n && o_last + WIN - 1 <= m &&
                               o_first + WIN - 1 <= d;
+            // Under the invariant (band of d-1 inside [2, WIN-3], of d-2 inside
+            // [1, WIN-2]) the odd step's live cells stay in [1, WIN-2] and the
+            // even step's in [0, WIN-2]; only the even step needs the check.
+            // The pair loop counts in ub = 2u (the bit offset of pair u in the
+            // code words); a live edge cell adds 64 on top, which ends the loop
+            // (2 * UMAX < 64) and leaves the pair count in the low bits.
+            const uint32_t ube = 2u * (uint32_t)P;
+            uint32_t ub = 0;
             if (fast) {
-                for (int u = 0; u < U; ++u) {
-                    const uint32_t ub = 2u * (uint32_t)u;
-                    step<true, false>(s, d + 2 * u, ub, tp, ti, sm, nd, G, m, n);
-                    step<false, false>(s, d + 2 * u + 1, ub, tp, ti, sm, nd, G, m, n);
-                }
+                do {
+                    step<true, false>(s, d + (int)ub, ub, tp, ti, sm, nd, G, X, m, n);
+                    const uint64_t e = step<false, false>(s, d + (int)ub + 1, ub, tp, ti, sm, nd, G, X, m, n);
+                    ub = next_pair(ub, e);
+                } while (ub < ube);
             } else {
-                for (int u = 0; u < U; ++u) {
-                    const uint32_t ub = 2u * (uint32_t)u;
-                    step<true, true>(s, d + 2 * u, ub, tp, ti, sm, nd, G, m, n);
-                    step<false, true>(s, d + 2 * u + 1, ub, tp, ti, sm, nd, G, m, n);
-                }
+                do {
+                    step<true, true>(s, d + (int)ub, ub, tp, ti, sm, nd, G, X, m, n);
+                    const uint64_t e = step<false, true>(s, d + (int)ub + 1, ub, tp, ti, sm, nd, G, X, m, n);
+                    ub = next_pair(ub, e);
+                } while (ub < ube);
             }
-            s.d = d + 2 * U;
+            const int u = (int)(ub & 63u) >> 1;
+            s.d = d + 2 * u;
             s.T = ti - G * s.d;
-            resolve(s);
+            resolve(s, d);
         }
         return kDone;
     }
