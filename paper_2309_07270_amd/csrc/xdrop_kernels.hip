@@ -60,6 +60,14 @@ __device__ __forceinline__ uint32_t code_at(const uint32_t *__restrict__ W, uint
     return (W[p >> 4] >> ((p & 15) * 2)) & 3u;
 }
 
+// bases p .. p+15 as 2-bit fields (base p in bits 0-1); reads one word past
+// the base p+15 at most, which the store's guard words cover
+__device__ __forceinline__ uint32_t codes16_at(const uint32_t *__restrict__ W, uint64_t p)
+{
+    const uint32_t *w = W + (p >> 4);
+    return __builtin_amdgcn_alignbit(w[1], w[0], (uint32_t)(p & 15) * 2u);
+}
+
 // Guard of the store: reads keep at least kGuardWords words (8192 bases) before
 // their first and after their last base, so a lane's code window -- which
 // starts within 2 windows + 64 bases of its sequence -- never leaves the store.
@@ -203,6 +211,12 @@ __global__ void accum_errors_kernel(const uint32_t *ctr, uint32_t *acc)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) prep_kernel(BatchDev b, StoreDev st, Tuning tu, int stage)
 {
+    // per-block histogram of bucket keys, flushed with one global atomic per bin
+    __shared__ uint32_t hist[kNumClasses * kNumBuckets];
+    if (stage) {
+        for (int i = threadIdx.x; i < kNumClasses * kNumBuckets; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+    }
     const uint32_t n = b.ctr[CtrLayout::kN];
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = r < n;
@@ -219,11 +233,18 @@ __global__ void __launch_bounds__(256) prep_kernel(BatchDev b, StoreDev st, Tuni
     if (ok) {
         const ReadInfo A = st.reads[R.read_a], B = st.reads[R.read_b];
         const uint32_t pb = R.strand ? B.len - R.pos_b - R.k : R.pos_b;
+        const uint64_t aseed = A.fwd + R.pos_a;
         const uint64_t bseed = R.strand ? B.rc + pb : B.fwd + pb;
-        int s = 0;
-        for (uint32_t t = 0; t < R.k; ++t)
-            s += code_at(st.words, A.fwd + R.pos_a + t) == code_at(st.words, bseed + t) ? R.match : R.mismatch;
-        b.seed[r] = s;
+        // seed score: mismatches of 16 bases at a time (xor of 2-bit codes)
+        uint32_t mism = 0;
+        for (uint32_t t = 0; t < R.k; t += 16) {
+            uint32_t x = codes16_at(st.words, aseed + t) ^ codes16_at(st.words, bseed + t);
+            x = (x | (x >> 1)) & 0x55555555u;
+            const uint32_t left = R.k - t;
+            if (left < 16) x &= (1u << (2u * left)) - 1u;
+            mism += (uint32_t)__builtin_popcount(x);
+        }
+        b.seed[r] = (int)(R.k - mism) * R.match + (int)mism * R.mismatch;
         cls = kAdaptiveClass;
         key0 = min(R.pos_a, pb);
         key1 = min(A.len - R.pos_a - R.k, B.len - pb - R.k);
@@ -242,10 +263,15 @@ __global__ void __launch_bounds__(256) prep_kernel(BatchDev b, StoreDev st, Tuni
             dst[q * qcap + base + before] = 2u * r;
             dst[q * qcap + base + before + 1] = 2u * r + 1u;
             if (stage) {
-                atomicAdd(&b.bucket_hist[q * kNumBuckets + bucket_of(key0)], 1u);
-                atomicAdd(&b.bucket_hist[q * kNumBuckets + bucket_of(key1)], 1u);
+                atomicAdd(&hist[q * kNumBuckets + bucket_of(key0)], 1u);
+                atomicAdd(&hist[q * kNumBuckets + bucket_of(key1)], 1u);
             }
         }
+    }
+    if (stage) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < kNumClasses * kNumBuckets; i += blockDim.x)
+            if (hist[i]) atomicAdd(&b.bucket_hist[i], hist[i]);
     }
 }
 
@@ -269,18 +295,34 @@ __global__ void bucket_scan_kernel(BatchDev b)
 
 __global__ void __launch_bounds__(256) bucket_scatter_kernel(BatchDev b, StoreDev st)
 {
+    // ranks within the block come from LDS atomics; one global atomic per
+    // (block, bucket) reserves the block's range (order inside a bucket is free)
+    __shared__ uint32_t cnt_l[kNumBuckets], base_l[kNumBuckets];
     const uint32_t qcap = 2u * b.cap;
-    const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t first = blockIdx.x * blockDim.x;
+    const uint32_t idx = first + threadIdx.x;
     for (int q = 0; q < kNumClasses; ++q) {
         const uint32_t cnt = b.ctr[CtrLayout::kStage + q];
-        if (idx >= cnt) continue;
-        const uint32_t t = b.qkey[q * qcap + idx];
-        const xdrop_record R = b.recs[t >> 1];
-        const ReadInfo A = st.reads[R.read_a], B = st.reads[R.read_b];
-        const uint32_t pb = R.strand ? B.len - R.pos_b - R.k : R.pos_b;
-        const uint32_t key = (t & 1) ? min(A.len - R.pos_a - R.k, B.len - pb - R.k) : min(R.pos_a, pb);
-        const uint32_t pos = atomicAdd(&b.bucket_hist[q * kNumBuckets + bucket_of(key)], 1u);
-        b.qbuf[q * qcap + pos] = t;
+        if (first >= cnt) continue;                  // uniform over the block
+        for (int i = threadIdx.x; i < kNumBuckets; i += blockDim.x) cnt_l[i] = 0;
+        __syncthreads();
+        int bk = -1;
+        uint32_t t = 0, rank = 0;
+        if (idx < cnt) {
+            t = b.qkey[q * qcap + idx];
+            const xdrop_record R = b.recs[t >> 1];
+            const ReadInfo A = st.reads[R.read_a], B = st.reads[R.read_b];
+            const uint32_t pb = R.strand ? B.len - R.pos_b - R.k : R.pos_b;
+            const uint32_t key = (t & 1) ? min(A.len - R.pos_a - R.k, B.len - pb - R.k) : min(R.pos_a, pb);
+            bk = bucket_of(key);
+            rank = atomicAdd(&cnt_l[bk], 1u);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < kNumBuckets; i += blockDim.x)
+            base_l[i] = cnt_l[i] ? atomicAdd(&b.bucket_hist[q * kNumBuckets + i], cnt_l[i]) : 0u;
+        __syncthreads();
+        if (bk >= 0) b.qbuf[q * qcap + base_l[bk] + rank] = t;
+        __syncthreads();
     }
 }
 
@@ -401,8 +443,10 @@ struct Window {
         int lo_s = 0, hi_s = 0;
         if (BOUNDS) {
             const int o = s.base + (d >> 1);
-            lo_s = max(0, d - n) - o;
-            hi_s = min(m, d) - o;
+            // only j <= n and i <= m can fail: a cell with i < 0 or j < 0 has
+            // no live predecessor (moves never decrease i or j from (0, 0))
+            lo_s = d - n - o;
+            hi_s = m - o;
         }
         uint64_t imp = 0, lm[C];
         int v[C];
@@ -628,9 +672,11 @@ struct Window {
             }
             int tp = s.T - X + G * d, ti = s.T + G * d;
             const int dlast = d + 2 * P - 1;
-            const int o_first = s.base + (d >> 1), o_last = s.base + (dlast >> 1);
-            const bool fast = o_first >= 0 && o_last >= dlast - n && o_last + WIN - 1 <= m &&
-                              o_first + WIN - 1 <= d;
+            // no clipping needed when every slot that can hold a candidate
+            // (0 .. WIN-2) of every anti-diagonal of the block has i <= m and
+            // j <= n; i >= 0 and j >= 0 hold for every candidate
+            const int o_last = s.base + (dlast >> 1);
+            const bool fast = o_last + WIN - 2 <= m && o_last >= dlast - n;
             // Under the invariant (band of d-1 inside [2, WIN-3], of d-2 inside
             // [1, WIN-2]) the odd step's live cells stay in [1, WIN-2] and the
             // even step's in [0, WIN-2]; only the even step needs the check.
