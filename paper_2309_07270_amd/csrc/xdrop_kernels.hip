@@ -349,12 +349,17 @@ enum : uint32_t { kDone = 0, kGrow = 1, kShrink = 2 };
 template <int C, bool COUNT, bool MA1, bool SIGF, int STRIDE = WMAX>
 struct Window {
     static constexpr int WIN = 64 * C;
-    static constexpr int NWC = (C + UMAX + 16) / 16;   // words of codes per lane and block
+    // pairs per block: two halves of UMAX pairs (one code load) for the
+    // adaptive widths, one half for the wide windows (register budget)
+    static constexpr int NH = C <= 4 ? 2 : 1;
+    static constexpr int PB = NH * UMAX;
+    static constexpr int NWC = (C + PB + 16) / 16;   // words of codes per lane and block
     static_assert(STRIDE >= WIN, "LDS stride must hold the window");
 
     int Z1[C];                // anti-diagonal d-1 (Z units: S + |gap| * d; NEG = dead)
     int Z2[C];                // anti-diagonal d-2
     uint32_t mmo[C], mme[C];  // per pair u: mismatch bit (bit 2u) or, SIGF, sigma field (bits 2u..2u+1)
+    uint32_t mmo2[C], mme2[C];  // the same for pairs UMAX .. 2*UMAX-1 (NH = 2)
 
     // deferred end cell (MA1): last improving anti-diagonal of the block, its
     // improvement mask over lanes and, per lane, the first improving slot r
@@ -581,6 +586,27 @@ struct Window {
         return ub;
     }
 
+    // Up to np <= UMAX pairs from odd anti-diagonal d0 on the current sigma
+    // words.  Under the invariant (band of d-1 inside [2, WIN-3], of d-2 inside
+    // [1, WIN-2]) the odd step's live cells stay in [1, WIN-2] and the even
+    // step's in [0, WIN-2]; only the even step needs the edge check.  The loop
+    // counts in ub = 2u (the bit offset of pair u in the code words); a live
+    // edge cell adds 64 on top, which ends the loop (2 * UMAX < 64) and
+    // leaves the pair count in the low bits.  Returns ub.
+    template <bool BOUNDS>
+    __device__ __forceinline__ uint32_t pairs(XState &s, int d0, int np, int &tp, int &ti, int sm, int nd, int G,
+                                              int X, int m, int n)
+    {
+        const uint32_t ube = 2u * (uint32_t)np;
+        uint32_t ub = 0;
+        do {
+            step<true, BOUNDS>(s, d0 + (int)ub, ub, tp, ti, sm, nd, G, X, m, n);
+            const uint64_t e = step<false, BOUNDS>(s, d0 + (int)ub + 1, ub, tp, ti, sm, nd, G, X, m, n);
+            ub = next_pair(ub, e);
+        } while (ub < ube);
+        return ub;
+    }
+
     // live slots over the last two anti-diagonals; false when both are dead
     __device__ __forceinline__ bool band(int &mn, int &mx) const
     {
@@ -600,7 +626,7 @@ struct Window {
     // Advance the extension block by block.  Returns kDone, or kGrow / kShrink
     // with the window saved to LDS and s.mn / s.mx set (shrink_width < 0: never).
     //
-    // A block covers up to UMAX anti-diagonal pairs (odd d, even d+1) with one
+    // A block covers up to PB anti-diagonal pairs (odd d, even d+1) with one
     // load of codes.  The odd step of a pair can add a candidate one slot to
     // the right of the band, the even step one slot to the left.  A block
     // starts with the live band of the last two anti-diagonals inside
@@ -643,7 +669,7 @@ struct Window {
                 s.base += delta;
             }
             const int d = s.d;
-            const int P = min(UMAX, (dend - d + 2) >> 1);   // pairs up to the far corner
+            const int P = min(PB, (dend - d + 2) >> 1);      // pairs up to the far corner
             // codes for this block: slot r of this lane meets a[A0 + C*lane + r + u
             // (+1 on even d)] and b[B0 - C*lane - r + u] at pair u
             const int e0 = (d - 1) >> 1;
@@ -653,21 +679,24 @@ struct Window {
             load_codes<NWC>(aseq, aph, A0 + C * lane, aw);
             load_codes<NWC>(bseq, bph, B0 - C * lane - (C - 1), bw);
 #pragma unroll
-            for (int r = 0; r < C; ++r) {
-                const uint32_t bb = codes16<NWC>(bw, C - 1 - r);
-                const uint32_t xo = codes16<NWC>(aw, r) ^ bb;
-                const uint32_t xe = codes16<NWC>(aw, r + 1) ^ bb;
-                const uint32_t mo = (xo | (xo >> 1)) & 0x55555555u;   // 1 = mismatch, at bit 2u
-                const uint32_t me = (xe | (xe >> 1)) & 0x55555555u;
-                if (SIGF) {
-                    // field u = sigma'' of pair u: sm ^ (mismatch ? sm ^ sx : 0)
-                    const uint32_t base_f = (uint32_t)sm * 0x55555555u;
-                    const uint32_t k = (uint32_t)(sm ^ sx);
-                    mmo[r] = base_f ^ ((k & 1u) ? mo : 0u) ^ ((k & 2u) ? (mo << 1) : 0u);
-                    mme[r] = base_f ^ ((k & 1u) ? me : 0u) ^ ((k & 2u) ? (me << 1) : 0u);
-                } else {
-                    mmo[r] = mo;
-                    mme[r] = me;
+            for (int h = 0; h < NH; ++h) {
+#pragma unroll
+                for (int r = 0; r < C; ++r) {
+                    const uint32_t bb = codes16<NWC>(bw, C - 1 - r + 16 * h);
+                    const uint32_t xo = codes16<NWC>(aw, r + 16 * h) ^ bb;
+                    const uint32_t xe = codes16<NWC>(aw, r + 1 + 16 * h) ^ bb;
+                    const uint32_t mo = (xo | (xo >> 1)) & 0x55555555u;   // 1 = mismatch, at bit 2u
+                    const uint32_t me = (xe | (xe >> 1)) & 0x55555555u;
+                    uint32_t fo = mo, fe = me;
+                    if (SIGF) {
+                        // field u = sigma'' of pair u: sm ^ (mismatch ? sm ^ sx : 0)
+                        const uint32_t base_f = (uint32_t)sm * 0x55555555u;
+                        const uint32_t k = (uint32_t)(sm ^ sx);
+                        fo = base_f ^ ((k & 1u) ? mo : 0u) ^ ((k & 2u) ? (mo << 1) : 0u);
+                        fe = base_f ^ ((k & 1u) ? me : 0u) ^ ((k & 2u) ? (me << 1) : 0u);
+                    }
+                    if (h == 0) { mmo[r] = fo; mme[r] = fe; }
+                    else { mmo2[r] = fo; mme2[r] = fe; }
                 }
             }
             int tp = s.T - X + G * d, ti = s.T + G * d;
@@ -677,31 +706,28 @@ struct Window {
             // j <= n; i >= 0 and j >= 0 hold for every candidate
             const int o_last = s.base + (dlast >> 1);
             const bool fast = o_last + WIN - 2 <= m && o_last >= dlast - n;
-            // Under the invariant (band of d-1 inside [2, WIN-3], of d-2 inside
-            // [1, WIN-2]) the odd step's live cells stay in [1, WIN-2] and the
-            // even step's in [0, WIN-2]; only the even step needs the check.
-            // The pair loop counts in ub = 2u (the bit offset of pair u in the
-            // code words); a live edge cell adds 64 on top, which ends the loop
-            // (2 * UMAX < 64) and leaves the pair count in the low bits.
-            const uint32_t ube = 2u * (uint32_t)P;
-            uint32_t ub = 0;
-            if (fast) {
-                do {
-                    step<true, false>(s, d + (int)ub, ub, tp, ti, sm, nd, G, X, m, n);
-                    const uint64_t e = step<false, false>(s, d + (int)ub + 1, ub, tp, ti, sm, nd, G, X, m, n);
-                    ub = next_pair(ub, e);
-                } while (ub < ube);
+            const int p0 = min(P, UMAX);
+            uint32_t ub = fast ? pairs<false>(s, d, p0, tp, ti, sm, nd, G, X, m, n)
+                               : pairs<true>(s, d, p0, tp, ti, sm, nd, G, X, m, n);
+            int u = (int)(ub & 63u) >> 1;
+            if (NH == 2 && ub < 64u && P > UMAX) {
+                // second half: end cell of the first, then its sigma words
+                resolve(s, d);
+                const int d1 = d + 2 * UMAX;
+#pragma unroll
+                for (int r = 0; r < C; ++r) {
+                    mmo[r] = mmo2[r];
+                    mme[r] = mme2[r];
+                }
+                ub = fast ? pairs<false>(s, d1, P - UMAX, tp, ti, sm, nd, G, X, m, n)
+                          : pairs<true>(s, d1, P - UMAX, tp, ti, sm, nd, G, X, m, n);
+                u = UMAX + ((int)(ub & 63u) >> 1);
+                resolve(s, d1);
             } else {
-                do {
-                    step<true, true>(s, d + (int)ub, ub, tp, ti, sm, nd, G, X, m, n);
-                    const uint64_t e = step<false, true>(s, d + (int)ub + 1, ub, tp, ti, sm, nd, G, X, m, n);
-                    ub = next_pair(ub, e);
-                } while (ub < ube);
+                resolve(s, d);
             }
-            const int u = (int)(ub & 63u) >> 1;
             s.d = d + 2 * u;
             s.T = ti - G * s.d;
-            resolve(s, d);
         }
         return kDone;
     }
