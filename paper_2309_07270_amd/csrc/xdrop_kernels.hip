@@ -424,10 +424,12 @@ struct Window {
     // and T_{d-1}, plus |gap| * d); on return they hold those of d+1.  Returns
     // the live cells of d in the two edge slots on either side of the window
     // (bit per lane).
-    template <bool ODD, bool BOUNDS>
-    __device__ __forceinline__ uint64_t step(XState &s, int d, uint32_t ub, int &tp, int &ti, int sm, int nd,
+    template <bool ODD, bool BOUNDS, int KU = -1>
+    __device__ __forceinline__ uint64_t step(XState &s, int d, uint32_t ub_rt, int &tp, int &ti, int sm, int nd,
                                              int G, int X, int m, int n)
     {
+        // KU >= 0: the pair offset is the compile-time constant KU (unrolled loop)
+        const uint32_t ub = KU >= 0 ? (uint32_t)KU : ub_rt;
         const int lane = lane_id();
         int t[C];
         // Gap predecessors come from the neighbouring slot of d-1, one lane
@@ -483,14 +485,25 @@ struct Window {
             // unit without a branch.
             uint64_t &li = ODD ? li_o : li_e;
             int &lu = ODD ? lu_o : lu_e;
-            asm volatile("s_cmp_lg_u64 %[imp], 0\n\t"
-                         "s_cselect_b64 %[li], %[imp], %[li]\n\t"
-                         "s_cselect_b32 %[lu], %[ub], %[lu]\n\t"
-                         "s_addc_u32 %[ti], %[ti], %[g]\n\t"
-                         "s_sub_i32 %[tp], %[ti], %[x]"
-                         : [li] "+s"(li), [lu] "+s"(lu), [ti] "+s"(ti), [tp] "=s"(tp)
-                         : [imp] "s"(imp), [ub] "s"(ub), [g] "s"(G), [x] "s"(X)
-                         : "scc");
+            if (KU >= 0) {
+                asm volatile("s_cmp_lg_u64 %[imp], 0\n\t"
+                             "s_cselect_b64 %[li], %[imp], %[li]\n\t"
+                             "s_cselect_b32 %[lu], %[ub], %[lu]\n\t"
+                             "s_addc_u32 %[ti], %[ti], %[g]\n\t"
+                             "s_sub_i32 %[tp], %[ti], %[x]"
+                             : [li] "+s"(li), [lu] "+s"(lu), [ti] "+s"(ti), [tp] "=s"(tp)
+                             : [imp] "s"(imp), [ub] "i"(KU < 0 ? 0 : KU), [g] "s"(G), [x] "s"(X)
+                             : "scc");
+            } else {
+                asm volatile("s_cmp_lg_u64 %[imp], 0\n\t"
+                             "s_cselect_b64 %[li], %[imp], %[li]\n\t"
+                             "s_cselect_b32 %[lu], %[ub], %[lu]\n\t"
+                             "s_addc_u32 %[ti], %[ti], %[g]\n\t"
+                             "s_sub_i32 %[tp], %[ti], %[x]"
+                             : [li] "+s"(li), [lu] "+s"(lu), [ti] "+s"(ti), [tp] "=s"(tp)
+                             : [imp] "s"(imp), [ub] "s"(ub), [g] "s"(G), [x] "s"(X)
+                             : "scc");
+            }
         } else if (MA1) {
             if (imp) {
                 last_d = d;
@@ -593,6 +606,38 @@ struct Window {
     // counts in ub = 2u (the bit offset of pair u in the code words); a live
     // edge cell adds 64 on top, which ends the loop (2 * UMAX < 64) and
     // leaves the pair count in the low bits.  Returns ub.
+    // UMAX pairs without clipping, unrolled and without a test between them:
+    // bit offsets and recorded pair offsets are immediates and the live masks
+    // of the even steps are OR-ed into acc.  Exact if acc ends with no edge
+    // lane set (then the invariant held before every pair); otherwise the
+    // caller restores the state and reruns the half with pairs<false>.
+    template <int K = 0>
+    __device__ __forceinline__ uint64_t pairs_spec(XState &s, int d0, int &tp, int &ti, int sm, int nd, int G,
+                                                   int X, int m, int n, uint64_t acc)
+    {
+        if constexpr (K == UMAX) {
+            return acc;
+        } else {
+            step<true, false, 2 * K>(s, d0 + 2 * K, 0u, tp, ti, sm, nd, G, X, m, n);
+            acc |= step<false, false, 2 * K>(s, d0 + 2 * K + 1, 0u, tp, ti, sm, nd, G, X, m, n);
+            return pairs_spec<K + 1>(s, d0, tp, ti, sm, nd, G, X, m, n, acc);
+        }
+    }
+
+    // one half of UMAX pairs at C = 1 without clipping: speculative run,
+    // rolled back and rerun with per-pair checks if an edge lane went live
+    __device__ __forceinline__ uint32_t half_c1(XState &s, int d0, int &tp, int &ti, int sm, int nd, int G, int X,
+                                                int m, int n)
+    {
+        const int z1 = Z1[0], z2 = Z2[0], tp0 = tp, ti0 = ti, luo = lu_o, lue = lu_e;
+        const uint64_t lio = li_o, lie = li_e, cells0 = s.cells;
+        const uint64_t acc = pairs_spec(s, d0, tp, ti, sm, nd, G, X, m, n, 0ull);
+        if (!(acc & 0xC000000000000003ull)) return 2u * UMAX;   // lanes 0, 1, 62, 63
+        Z1[0] = z1; Z2[0] = z2; tp = tp0; ti = ti0;
+        lu_o = luo; lu_e = lue; li_o = lio; li_e = lie; s.cells = cells0;
+        return pairs<false>(s, d0, UMAX, tp, ti, sm, nd, G, X, m, n);
+    }
+
     template <bool BOUNDS>
     __device__ __forceinline__ uint32_t pairs(XState &s, int d0, int np, int &tp, int &ti, int sm, int nd, int G,
                                               int X, int m, int n)
@@ -707,8 +752,13 @@ struct Window {
             const int o_last = s.base + (dlast >> 1);
             const bool fast = o_last + WIN - 2 <= m && o_last >= dlast - n;
             const int p0 = min(P, UMAX);
-            uint32_t ub = fast ? pairs<false>(s, d, p0, tp, ti, sm, nd, G, X, m, n)
-                               : pairs<true>(s, d, p0, tp, ti, sm, nd, G, X, m, n);
+            uint32_t ub;
+            if (C == 1 && MA1 && fast && p0 == UMAX)
+                ub = half_c1(s, d, tp, ti, sm, nd, G, X, m, n);
+            else if (fast)
+                ub = pairs<false>(s, d, p0, tp, ti, sm, nd, G, X, m, n);
+            else
+                ub = pairs<true>(s, d, p0, tp, ti, sm, nd, G, X, m, n);
             int u = (int)(ub & 63u) >> 1;
             if (NH == 2 && ub < 64u && P > UMAX) {
                 // second half: end cell of the first, then its sigma words
@@ -719,8 +769,12 @@ struct Window {
                     mmo[r] = mmo2[r];
                     mme[r] = mme2[r];
                 }
-                ub = fast ? pairs<false>(s, d1, P - UMAX, tp, ti, sm, nd, G, X, m, n)
-                          : pairs<true>(s, d1, P - UMAX, tp, ti, sm, nd, G, X, m, n);
+                if (C == 1 && MA1 && fast && P == PB)
+                    ub = half_c1(s, d1, tp, ti, sm, nd, G, X, m, n);
+                else if (fast)
+                    ub = pairs<false>(s, d1, P - UMAX, tp, ti, sm, nd, G, X, m, n);
+                else
+                    ub = pairs<true>(s, d1, P - UMAX, tp, ti, sm, nd, G, X, m, n);
                 u = UMAX + ((int)(ub & 63u) >> 1);
                 resolve(s, d1);
             } else {
