@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=6.0)
     ap.add_argument("--serve-points", default="0.1,0.3,0.5,0.7,0.9,1.0,1.1,1.2")
     ap.add_argument("--producers", type=int, default=25)
+    ap.add_argument("--tuning-cache", default=None,
+                    help="launch-parameter file: loaded if it exists (no autotune), else written by the autotuner")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -120,11 +122,17 @@ def main():
     d_cells = torch.zeros(n, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
 
-    ctx = X.Context(wl.store, mode=X.MODE_PERSISTENT)
-    # autotuner (untimed): launch parameters chosen on a 10,000-record sample
+    # autotuner (untimed): launch parameters chosen on the whole batch (every
+    # setting gives the same results), or taken from a tuning file
     t0 = time.time()
-    tuning, tune_ms = ctx.autotune(recs[:10000])
-    log(f"autotune: {tuning} ({tune_ms:.2f} ms on the sample, {time.time() - t0:.1f}s)")
+    if args.tuning_cache and os.path.exists(args.tuning_cache):
+        ctx = X.Context(wl.store, mode=X.MODE_PERSISTENT, tuning_cache=args.tuning_cache)
+        tuning = ctx.tuning()
+        log(f"tuning from {args.tuning_cache}: {tuning}")
+    else:
+        ctx = X.Context(wl.store, mode=X.MODE_PERSISTENT)
+        tuning, tune_ms = ctx.autotune(recs, cache_path=args.tuning_cache)
+        log(f"autotune: {tuning} ({tune_ms:.2f} ms per batch, {time.time() - t0:.1f}s)")
     # counting pass (untimed): exact candidate cells of every extension
     t = ctx.submit_device(d_recs, n, d_out, d_cells, stream=stream)
     ctx.wait(t)
@@ -282,7 +290,9 @@ def serve_main(args):
     wl = W.make_workload(name, pairs=args.pairs)
     recs = wl.records
     log(f"serve workload {name}: {len(recs)} records, gen {time.time() - t0:.1f}s")
-    ctx = X.Context(wl.store, max_inflight=8)
+    ctx = X.Context(wl.store, max_inflight=8,
+                    tuning_cache=args.tuning_cache if args.tuning_cache and os.path.exists(args.tuning_cache)
+                    else None)
     # exact cells of every record (one counting pass), for GCUPS of each batch
     cells = np.zeros(len(recs), np.uint64)
     for off in range(0, len(recs), 200000):
