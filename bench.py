@@ -43,6 +43,22 @@ def kernel_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
+def measured_valu_peak():
+    """int32 lane-ops/s of independent add/max chains at full occupancy
+    (libxdrop_probe.so), or None when the probe library is not built."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2309_07270_amd", "libxdrop_probe.so")
+    if not os.path.exists(path):
+        return None
+    lib = ctypes.CDLL(path)
+    lib.xdrop_probe_valu_ops.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]
+    ops, ms = ctypes.c_double(), ctypes.c_double()
+    if lib.xdrop_probe_valu_ops(0, 100000, ctypes.byref(ops), ctypes.byref(ms)) != 0:
+        return None
+    return ops.value
+
+
 def pct(xs, q):
     import numpy as np
     return float(np.percentile(np.asarray(xs, dtype=float), q)) if len(xs) else None
@@ -65,7 +81,7 @@ def read_traffic(stage_name: str, workload: str):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c1")
     ap.add_argument("--pairs", type=int, default=None, help="shrink the workload (tests only)")
@@ -81,6 +97,10 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=6.0)
     ap.add_argument("--serve-points", default="0.1,0.3,0.5,0.7,0.9,1.0,1.1,1.2")
     ap.add_argument("--producers", type=int, default=25)
+    ap.add_argument("--granularity", default="0",
+                    help="serving hand-off granularity ablation: comma list of sub-batch sizes "
+                         "(0 = whole batch); each producer batch is split into sub-batches "
+                         "submitted back to back and waited together")
     ap.add_argument("--tuning-cache", default=None,
                     help="launch-parameter file: loaded if it exists (no autotune), else written by the autotuner")
     args = ap.parse_args()
@@ -171,7 +191,7 @@ def main():
     pc = X.Context(wl.store, mode=X.MODE_PERSISTENT, profile=True)
     pc.set_tuning(**tuning)
     pst = pc.wait(pc.submit_device(d_recs, n, d_out, d_cells, stream=stream))
-    stage_cells, stage_tasks = pst["stage_cells"], pst["stage_tasks"]
+    stage_cells, stage_tasks, stage_slots = pst["stage_cells"], pst["stage_tasks"], pst["stage_slots"]
     p_elapsed, p_lat, stage_ms = timed(pc, args.steps, 1)
     pc.close()
     p_gcups = total_cells * args.steps / p_elapsed / 1e9
@@ -184,13 +204,20 @@ def main():
     dom_name = X.STAGE_NAMES[dom]
     achieved_ops = stage_cells[dom] * OPS_PER_CELL / (stage_ms[dom] / 1e3) if stage_ms[dom] > 0 else 0.0
     traffic = read_traffic(dom_name, args.workload)
+    peak_meas = measured_valu_peak()
+    if peak_meas:
+        log(f"measured int32 VALU peak: {peak_meas / 1e12:.1f} T ops/s (spec-derived {SPEC_PEAK_INT32_OPS / 1e12:.1f})")
     roofline = {"bound": "alu", "kernel": dom_name, "achieved": achieved_ops / 1e12,
                 "peak": SPEC_PEAK_INT32_OPS / 1e12, "unit": "Tint32op/s",
                 "frac": achieved_ops / SPEC_PEAK_INT32_OPS,
+                "measured_peak": peak_meas / 1e12 if peak_meas else None,
+                "frac_of_measured": achieved_ops / peak_meas if peak_meas else None,
                 "traffic": traffic,
                 "units_per_launch": int(stage_cells[dom]), "unit_name": "cells",
                 "ops_per_unit": OPS_PER_CELL, "launch_ms": float(stage_ms[dom]),
-                "tasks_per_launch": int(stage_tasks[dom])}
+                "tasks_per_launch": int(stage_tasks[dom]),
+                # secondary bound: cells / window lane-steps of the kernel's extensions
+                "lane_occupancy": stage_cells[dom] / stage_slots[dom] if stage_slots[dom] else None}
 
     out = {"metric": "X-drop GCUPS + alignments/s on 1 GPU, batched vs plain; p50/p99 latency",
            "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
@@ -209,7 +236,8 @@ def main():
                        "profiled_launches": {"gcups": round(p_gcups, 2),
                                              "stage_ms": dict(zip(X.STAGE_NAMES, np.round(stage_ms, 4).tolist())),
                                              "stage_cells": dict(zip(X.STAGE_NAMES, [int(v) for v in stage_cells])),
-                                             "stage_tasks": dict(zip(X.STAGE_NAMES, [int(v) for v in stage_tasks]))}},
+                                             "stage_tasks": dict(zip(X.STAGE_NAMES, [int(v) for v in stage_tasks])),
+                                             "stage_slots": dict(zip(X.STAGE_NAMES, [int(v) for v in stage_slots]))}},
            "roofline": roofline}
 
     if args.kernel_only:
@@ -263,6 +291,16 @@ def main():
                                "sample": f"first {S} records of {args.workload} ({ref_cells} cells, {c_el:.1f} s)"}
         out["parity_sample"] = f"{int(same.sum())}/{S} records bit-exact (results and cells) vs oracle"
         log(f"cpu oracle: {ref_cells / c_el / 1e9:.3f} GCUPS on {used} threads; parity {int(same.sum())}/{S}")
+        # the same oracle on one host thread, over a tenth of the sample
+        S1 = max(1, S // 10)
+        c0 = time.perf_counter()
+        ref1, _ = oracle.batch(wl.store.codes, wl.store.off, wl.store.length, recs[:S1], nthreads=1)
+        c1_el = time.perf_counter() - c0
+        cells1 = int((ref1["cells_left"] + ref1["cells_right"]).sum())
+        out["cpu_baseline_1core"] = {"value": round(cells1 / c1_el / 1e9, 3), "unit": "GCUPS", "cores": 1,
+                                     "kind": "oracle",
+                                     "sample": f"first {S1} records of {args.workload} ({cells1} cells, {c1_el:.1f} s)"}
+        log(f"cpu oracle, 1 thread: {cells1 / c1_el / 1e9:.3f} GCUPS")
 
     print(json.dumps(out))
 
@@ -307,7 +345,7 @@ def serve_main(args):
         s0 = int(r.integers(0, len(recs) - z))
         return s0, z
 
-    def run_phase(rate, seconds, closed):
+    def run_phase(rate, seconds, closed, gran=0):
         lat, done_recs, done_cells = [], [0], [0]
         lock = threading.Lock()
         t_begin = time.perf_counter()
@@ -328,8 +366,12 @@ def serve_main(args):
                     if t_next - t_begin > seconds:
                         break
                 s0, z = batch_at(r)
-                tk, out, _ = ctx.submit(recs[s0:s0 + z])
-                ctx.wait(tk)
+                if gran <= 0 or z <= gran:
+                    ctx.wait(ctx.submit(recs[s0:s0 + z])[0])
+                else:
+                    tks = [ctx.submit(recs[s0 + o:s0 + min(o + gran, z)])[0] for o in range(0, z, gran)]
+                    for tk in tks:
+                        ctx.wait(tk)
                 t_end = time.perf_counter()
                 with lock:
                     lat.append((t_end - t_next) * 1e3)
@@ -346,21 +388,37 @@ def serve_main(args):
                 "achieved_batches_per_s": len(lat) / el, "alignments_per_s": done_recs[0] / el,
                 "gcups": done_cells[0] / el / 1e9, "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99)}
 
-    run_phase(1.0, 1.0, True)  # warm-up: slots, graphs
-    sat = run_phase(1.0, args.serve_seconds, True)
-    log(f"saturated: {sat['achieved_batches_per_s']:.1f} batches/s, {sat['gcups']:.1f} GCUPS")
-    points = []
-    for f in [float(x) for x in args.serve_points.split(",")]:
-        rate = f * sat["achieved_batches_per_s"]
-        r = run_phase(rate, args.serve_seconds, False)
-        r["load_fraction"] = f
-        points.append(r)
-        log(f"load {f:.1f}: {r['achieved_batches_per_s']:.1f} b/s, p50 {r['p50_ms']:.1f} ms, p99 {r['p99_ms']:.1f} ms")
+    def sweep(gran):
+        run_phase(1.0, 1.0, True, gran)  # warm-up: slots, graphs
+        sat = run_phase(1.0, args.serve_seconds, True, gran)
+        log(f"sub-batch {gran}: saturated {sat['achieved_batches_per_s']:.1f} batches/s, {sat['gcups']:.1f} GCUPS")
+        points = []
+        for f in [float(x) for x in args.serve_points.split(",")]:
+            rate = f * sat["achieved_batches_per_s"]
+            r = run_phase(rate, args.serve_seconds, False, gran)
+            r["load_fraction"] = f
+            points.append(r)
+            log(f"sub-batch {gran}, load {f:.1f}: {r['achieved_batches_per_s']:.1f} b/s, "
+                f"p50 {r['p50_ms']:.1f} ms, p99 {r['p99_ms']:.1f} ms")
+        return sat, points
+
+    grans = [int(x) for x in args.granularity.split(",")]
+    workload = (f"{name}: {len(recs)}-record pool, batches U[1000,50000], {P} producers, "
+                f"Poisson arrivals, host-submitted batches")
+    if grans == [0]:
+        sat, points = sweep(0)
+        ctx.close()
+        print(json.dumps({"metric": "serving loop: throughput and p50/p99 batch latency vs offered load",
+                          "workload": workload, "unit": "GCUPS", "saturated": sat, "points": points}))
+        return
+    runs = []
+    for g in grans:
+        sat, points = sweep(g)
+        runs.append({"sub_batch": g, "saturated": sat, "points": points})
     ctx.close()
-    print(json.dumps({"metric": "serving loop: throughput and p50/p99 batch latency vs offered load",
-                      "workload": f"{name}: {len(recs)}-record pool, batches U[1000,50000], {P} producers, "
-                                  f"Poisson arrivals, host-submitted batches",
-                      "unit": "GCUPS", "saturated": sat, "points": points}))
+    print(json.dumps({"metric": "serving hand-off granularity: whole batch vs sub-batches, throughput and "
+                                "p50/p99 producer-batch latency vs offered load",
+                      "workload": workload, "unit": "GCUPS", "runs": runs}))
 
 
 if __name__ == "__main__":

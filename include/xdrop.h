@@ -131,6 +131,9 @@ typedef struct {
                                                completed (cell counting, persistent
                                                form only)                  */
     uint64_t stage_tasks[XDROP_NUM_STAGES]; /* extensions each stage completed (idem) */
+    uint64_t stage_slots[XDROP_NUM_STAGES]; /* window lane-steps those extensions took
+                                               (idem); stage_cells / stage_slots is
+                                               the lane occupancy of the stage     */
 } xdrop_batch_stats;
 
 /* Create a context on cfg->device: packs the reads to 2 bits per base (both

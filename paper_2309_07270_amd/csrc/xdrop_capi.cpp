@@ -93,6 +93,7 @@ struct Ticket {
     double stage_ms[XDROP_NUM_STAGES] = {};
     uint64_t stage_cells[XDROP_NUM_STAGES] = {};
     uint64_t stage_tasks[XDROP_NUM_STAGES] = {};
+    uint64_t stage_slots[XDROP_NUM_STAGES] = {};
 };
 
 struct Slot {
@@ -235,7 +236,7 @@ size_t slot_bytes(uint32_t cap)
     add((size_t)kNumClasses * 2 * n * sizeof(uint32_t));   // qkey
     add(CtrLayout::kWords * sizeof(uint32_t) + 64);
     add((size_t)kNumClasses * kNumBuckets * sizeof(uint32_t));
-    add(16 * sizeof(unsigned long long));
+    add(kStageSumWords * sizeof(unsigned long long));
     return b;
 }
 
@@ -282,7 +283,7 @@ void alloc_slot_buffers(xdrop_ctx *c, Slot &s, uint32_t cap)
     s.dev.ctr = (uint32_t *)take(CtrLayout::kWords * sizeof(uint32_t) + 64);
     s.d_n = s.dev.ctr + CtrLayout::kWords;
     s.dev.bucket_hist = (uint32_t *)take((size_t)kNumClasses * kNumBuckets * sizeof(uint32_t));
-    s.dev.stage_sum = (unsigned long long *)take(16 * sizeof(unsigned long long));
+    s.dev.stage_sum = (unsigned long long *)take(kStageSumWords * sizeof(unsigned long long));
     s.dev.cap = cap;
     // generic-kernel scratch: three anti-diagonals per wavefront
     s.generic_waves = (uint32_t)((std::max(4, c->tune.generic_waves) + 3) / 4 * 4);   // whole blocks of 4
@@ -293,7 +294,7 @@ void alloc_slot_buffers(xdrop_ctx *c, Slot &s, uint32_t cap)
     HIP_TRY(hipHostMalloc((void **)&s.h_res, n * sizeof(xdrop_result), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void **)&s.h_cells, n * sizeof(uint64_t), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void **)&s.h_misc, 64, hipHostMallocDefault));
-    HIP_TRY(hipHostMalloc((void **)&s.h_stage, 16 * sizeof(unsigned long long), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void **)&s.h_stage, kStageSumWords * sizeof(unsigned long long), hipHostMallocDefault));
     if (c->profile) {
         // plain form: one event set per chunk; persistent form: one set
         const size_t sets = c->mode == XDROP_MODE_PLAIN ? (cap + kPlainChunk - 1) / kPlainChunk : 1;
@@ -416,7 +417,7 @@ void run_batch(xdrop_ctx *c, Slot &sl, Ticket &t)
     const uint32_t *err_src = c->mode == XDROP_MODE_PERSISTENT ? sl.dev.ctr + CtrLayout::kErrors : sl.d_n + 1;
     HIP_TRY(hipMemcpyAsync(sl.h_misc + 1, err_src, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     if (count && c->mode == XDROP_MODE_PERSISTENT)
-        HIP_TRY(hipMemcpyAsync(sl.h_stage, sl.dev.stage_sum, 16 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(sl.h_stage, sl.dev.stage_sum, kStageSumWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(sl.ev2, s));
     HIP_TRY(hipEventSynchronize(sl.ev2));
     float ms = 0.f;
@@ -438,6 +439,7 @@ void run_batch(xdrop_ctx *c, Slot &sl, Ticket &t)
         for (int k = 0; k < XDROP_NUM_STAGES; ++k) {
             t.stage_cells[k] = sl.h_stage[k];
             t.stage_tasks[k] = sl.h_stage[8 + k];
+            t.stage_slots[k] = sl.h_stage[16 + k];
         }
     }
     const uint32_t errors = sl.h_misc[1];
@@ -826,6 +828,7 @@ xdrop_status xdrop_batch_wait(xdrop_ctx *c, xdrop_ticket id, int64_t timeout_us,
             stats->stage_ms[k] = t->stage_ms[k];
             stats->stage_cells[k] = t->stage_cells[k];
             stats->stage_tasks[k] = t->stage_tasks[k];
+            stats->stage_slots[k] = t->stage_slots[k];
         }
     }
     return t->status;

@@ -25,7 +25,8 @@ struct TaskOut {
     int32_t score;
     int32_t i, j;
     uint32_t status;   // class that completed the task (stage index - 1)
-    uint64_t cells;
+    uint64_t cells;    // candidate cells (cell counting only)
+    uint64_t slots;    // window lanes stepped over: slot-steps of the window (cell counting only)
 };
 
 enum : uint32_t { kStatusDone = 0, kStatusOverflow = 1 };
@@ -46,6 +47,8 @@ constexpr int kNumStages = kNumClasses + 2;   // ingest, classes..., finalize
 constexpr int kNumBuckets = 64;
 
 // Device buffers of one batch (all device pointers).
+constexpr int kStageSumWords = 24;
+
 struct BatchDev {
     const xdrop_record *recs;
     xdrop_result *res;
@@ -57,7 +60,7 @@ struct BatchDev {
     uint32_t *qkey;           // unsorted queue staging: (task id) per class, capacity 2*cap
     uint32_t *ctr;            // counters, see CtrLayout
     uint32_t *bucket_hist;    // kNumClasses * kNumBuckets
-    unsigned long long *stage_sum;  // [0..7] cells, [8..15] tasks completed per stage (1 + class)
+    unsigned long long *stage_sum;  // kStageSumWords: [0..7] cells, [8..15] tasks, [16..23] slot-steps per stage (1 + class)
     uint32_t cap;             // record capacity of the buffers
 };
 

@@ -197,7 +197,7 @@ __global__ void reset_kernel(uint32_t *ctr, uint32_t *hist, unsigned long long *
     const int t = threadIdx.x;
     if (t < CtrLayout::kN) ctr[t] = 0;
     if (t == 0) ctr[CtrLayout::kN] = n_src ? *n_src : n_imm;
-    if (t < 16) stage_sum[t] = 0ull;
+    if (t < kStageSumWords) stage_sum[t] = 0ull;
     for (int i = t; i < kNumClasses * kNumBuckets; i += blockDim.x) hist[i] = 0;
 }
 
@@ -336,6 +336,7 @@ struct XState {
     int base;       // o_d = base + floor(d/2): i of slot 0 on anti-diagonal d
     int T, bi, bj;  // best score so far and its cell
     uint64_t cells;
+    uint64_t slots; // slot-steps of the windows that ran the extension (cell counting)
     int mn, mx;     // live slots over the last two anti-diagonals (on kGrow / kShrink)
 };
 
@@ -378,7 +379,7 @@ struct Window {
         const int s0 = WIN / 2 - 1;
         s.base = -s0;
         s.d = 1;
-        s.T = 0; s.bi = 0; s.bj = 0; s.cells = 0;
+        s.T = 0; s.bi = 0; s.bj = 0; s.cells = 0; s.slots = 0;
         s.mn = s.mx = s0;
 #pragma unroll
         for (int r = 0; r < C; ++r) {
@@ -457,6 +458,7 @@ struct Window {
         }
         uint64_t imp = 0, lm[C];
         int v[C];
+        if (COUNT) s.slots += (uint64_t)WIN;
 #pragma unroll
         for (int r = 0; r < C; ++r) {
             const uint32_t w = ODD ? mmo[r] : mme[r];
@@ -630,11 +632,11 @@ struct Window {
                                                 int m, int n)
     {
         const int z1 = Z1[0], z2 = Z2[0], tp0 = tp, ti0 = ti, luo = lu_o, lue = lu_e;
-        const uint64_t lio = li_o, lie = li_e, cells0 = s.cells;
+        const uint64_t lio = li_o, lie = li_e, cells0 = s.cells, slots0 = s.slots;
         const uint64_t acc = pairs_spec(s, d0, tp, ti, sm, nd, G, X, m, n, 0ull);
         if (!(acc & 0xC000000000000003ull)) return 2u * UMAX;   // lanes 0, 1, 62, 63
         Z1[0] = z1; Z2[0] = z2; tp = tp0; ti = ti0;
-        lu_o = luo; lu_e = lue; li_o = lio; li_e = lie; s.cells = cells0;
+        lu_o = luo; lu_e = lue; li_o = lio; li_e = lie; s.cells = cells0; s.slots = slots0;
         return pairs<false>(s, d0, UMAX, tp, ti, sm, nd, G, X, m, n);
     }
 
@@ -891,7 +893,7 @@ __global__ void __launch_bounds__(256) adaptive_kernel(BatchDev b, StoreDev st, 
             ok = run_adaptive<COUNT, true, false>(st.words, st.max_base, k, lds, s, grow_margin, shrink_margin);
         if (ok) {
             TaskOut o;   // every lane stores the same (wave-uniform) values
-            o.score = s.T; o.i = s.bi; o.j = s.bj; o.status = (uint32_t)cls; o.cells = s.cells;
+            o.score = s.T; o.i = s.bi; o.j = s.bj; o.status = (uint32_t)cls; o.cells = s.cells; o.slots = s.slots;
             b.tout[t] = o;
         } else {
             const uint32_t pos = wave_fetch_add(&b.ctr[CtrLayout::kCount + cls + 1], 1u);
@@ -930,7 +932,7 @@ __global__ void __launch_bounds__(256) wide_kernel(BatchDev b, StoreDev st, int 
         }
         if (status == kDone) {
             TaskOut o;
-            o.score = s.T; o.i = s.bi; o.j = s.bj; o.status = (uint32_t)cls; o.cells = s.cells;
+            o.score = s.T; o.i = s.bi; o.j = s.bj; o.status = (uint32_t)cls; o.cells = s.cells; o.slots = s.slots;
             b.tout[t] = o;
         } else {
             const uint32_t pos = wave_fetch_add(&b.ctr[CtrLayout::kCount + cls + 1], 1u);
@@ -954,7 +956,7 @@ __device__ void generic_run(const uint32_t *__restrict__ W, const Geo &g, int X,
     P1[0] = 0;   // every lane writes the same value
     __threadfence_block();
     int T = 0, bi = 0, bj = 0;
-    uint64_t cells = 0;
+    uint64_t cells = 0, slots = 0;
     bool prev_dead = false;
     for (int d = 1; d <= m + n; ++d) {
         const int ilo = max(0, d - n), ihi = min(m, d);
@@ -987,7 +989,10 @@ __device__ void generic_run(const uint32_t *__restrict__ W, const Geo &g, int X,
             const bool lv = cand && v >= thr;
             // lanes past the range write an index that is never read (no divergent branch)
             P0[act ? i : dummy] = lv ? v : NEG;
-            if (COUNT) cells += (uint64_t)__builtin_popcountll(ballot(cand));
+            if (COUNT) {
+                cells += (uint64_t)__builtin_popcountll(ballot(cand));
+                slots += 64u;
+            }
             const uint64_t lmask = ballot(lv);
             if (lmask) {
                 if (nhi < 0) nlo = i0 + __builtin_ctzll(lmask);
@@ -1009,7 +1014,7 @@ __device__ void generic_run(const uint32_t *__restrict__ W, const Geo &g, int X,
         if (!live && prev_dead) break;
         prev_dead = !live;
     }
-    o.score = T; o.i = bi; o.j = bj; o.status = (uint32_t)kGenericClass; o.cells = cells;
+    o.score = T; o.i = bi; o.j = bj; o.status = (uint32_t)kGenericClass; o.cells = cells; o.slots = slots;
 }
 
 template <bool COUNT>
@@ -1037,38 +1042,51 @@ __global__ void __launch_bounds__(256) generic_kernel(BatchDev b, StoreDev st, i
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) finalize_kernel(BatchDev b, StoreDev st, int stage_sums)
 {
+    // per-stage totals (cells, extensions and slot-steps of each class) are
+    // summed in LDS, then added with one global atomic per counter and block
+    __shared__ unsigned long long acc[kStageSumWords];
+    if (stage_sums) {
+        if (threadIdx.x < kStageSumWords) acc[threadIdx.x] = 0ull;
+        __syncthreads();
+    }
     const uint32_t n = b.ctr[CtrLayout::kN];
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    if (stage_sums && b.valid[r]) {
-        // per-stage totals: cells and extensions completed by each class
+    const bool ok = r < n && b.valid[r];
+    if (stage_sums && ok) {
         for (int s = 0; s < 2; ++s) {
             const TaskOut o = b.tout[2 * r + s];
             const int stg = 1 + (int)o.status;
-            atomicAdd(&b.stage_sum[stg], (unsigned long long)o.cells);
-            atomicAdd(&b.stage_sum[8 + stg], 1ull);
+            atomicAdd(&acc[stg], (unsigned long long)o.cells);
+            atomicAdd(&acc[8 + stg], 1ull);
+            atomicAdd(&acc[16 + stg], (unsigned long long)o.slots);
         }
     }
-    xdrop_result out{};
-    uint64_t c = 0;
-    if (b.valid[r]) {
-        const xdrop_record R = b.recs[r];
-        const ReadInfo B = st.reads[R.read_b];
-        const uint32_t pb = R.strand ? B.len - R.pos_b - R.k : R.pos_b;
-        const TaskOut L = b.tout[2 * r], Rt = b.tout[2 * r + 1];
-        const int s = b.seed[r];
-        out.left_score = L.score;
-        out.right_score = Rt.score;
-        out.seed_score = s;
-        out.score = L.score + s + Rt.score;
-        out.a_begin = R.pos_a - (uint32_t)L.i;
-        out.a_end = R.pos_a + R.k + (uint32_t)Rt.i;
-        out.b_begin = pb - (uint32_t)L.j;
-        out.b_end = pb + R.k + (uint32_t)Rt.j;
-        c = L.cells + Rt.cells;
+    if (r < n) {
+        xdrop_result out{};
+        uint64_t c = 0;
+        if (ok) {
+            const xdrop_record R = b.recs[r];
+            const ReadInfo B = st.reads[R.read_b];
+            const uint32_t pb = R.strand ? B.len - R.pos_b - R.k : R.pos_b;
+            const TaskOut L = b.tout[2 * r], Rt = b.tout[2 * r + 1];
+            const int s = b.seed[r];
+            out.left_score = L.score;
+            out.right_score = Rt.score;
+            out.seed_score = s;
+            out.score = L.score + s + Rt.score;
+            out.a_begin = R.pos_a - (uint32_t)L.i;
+            out.a_end = R.pos_a + R.k + (uint32_t)Rt.i;
+            out.b_begin = pb - (uint32_t)L.j;
+            out.b_end = pb + R.k + (uint32_t)Rt.j;
+            c = L.cells + Rt.cells;
+        }
+        b.res[r] = out;
+        if (b.cells) b.cells[r] = c;
     }
-    b.res[r] = out;
-    if (b.cells) b.cells[r] = c;
+    if (stage_sums) {
+        __syncthreads();
+        if (threadIdx.x < kStageSumWords && acc[threadIdx.x]) atomicAdd(&b.stage_sum[threadIdx.x], acc[threadIdx.x]);
+    }
 }
 
 // ---------------------------------------------------------------------------

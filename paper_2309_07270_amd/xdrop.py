@@ -48,7 +48,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("records", ctypes.c_uint64), ("cells", ctypes.c_uint64), ("queue_ms", ctypes.c_double),
                 ("device_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("stage_ms", ctypes.c_double * NUM_STAGES), ("stage_cells", ctypes.c_uint64 * NUM_STAGES),
-                ("stage_tasks", ctypes.c_uint64 * NUM_STAGES)]
+                ("stage_tasks", ctypes.c_uint64 * NUM_STAGES), ("stage_slots", ctypes.c_uint64 * NUM_STAGES)]
 
     def as_dict(self):
         out = {}

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     assert W.RECORD_DTYPE.itemsize == 32 and W.RESULT_DTYPE.itemsize == 32
-    assert ctypes.sizeof(X.Stats) == 8 + 8 + 3 * 8 + 3 * 8 * X.NUM_STAGES
+    assert ctypes.sizeof(X.Stats) == 8 + 8 + 3 * 8 + 4 * 8 * X.NUM_STAGES
     # field offsets of xdrop_record as declared
     offs = {n: W.RECORD_DTYPE.fields[n][1] for n in W.RECORD_DTYPE.names}
     assert offs == {"read_a": 0, "read_b": 4, "pos_a": 8, "pos_b": 12, "k": 16, "strand": 18, "pad": 19,

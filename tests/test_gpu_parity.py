@@ -178,3 +178,33 @@ def test_autotune_and_tuning_cache(xd, c0, tmp_path):
         ctx2.set_tuning(waves_per_cu=4, buckets=0, grow_margin=2, shrink_margin=1, generic_waves=8)
         res2, cells2, _ = ctx2.run(wl.records, count_cells=True)
     assert_same(res2, cells2, ref)
+
+
+def test_paper_settings_k31_x15(xd):
+    # the paper's own runs use k = 31 and an X-drop of 15 ("Results",
+    # experimental setup); c1-shaped reads on a smaller genome
+    wl = W.make_workload("c1", pairs=3000, k=31, x_choices=(15,), genome=1_000_000)
+    ref, _ = oracle.batch(wl.store.codes, wl.store.off, wl.store.length, wl.records)
+    note("paper settings: k=31, X=15, 3000 c1-shaped records")
+    for mode in (0, 1):
+        with xd.Context(wl.store, mode=mode) as ctx:
+            res, cells, _ = ctx.run(wl.records, count_cells=True)
+        assert_same(res, cells, ref)
+    assert np.all(res["seed_score"] == 31)
+
+
+def test_stage_counters_and_lane_occupancy(xd, c0):
+    # per-stage totals of a counting pass: cells and tasks add up to the
+    # per-record counts, and each stage's window lane-steps bound its cells
+    wl, ref = c0
+    note("stage counters (cells, tasks, lane-steps)")
+    with xd.Context(wl.store) as ctx:
+        _, cells, st = ctx.run(wl.records, count_cells=True)
+    sc = np.array(st["stage_cells"], np.uint64)
+    stt = np.array(st["stage_tasks"], np.uint64)
+    ss = np.array(st["stage_slots"], np.uint64)
+    assert int(sc.sum()) == int(cells.sum())
+    assert int(stt.sum()) == 2 * len(wl.records)
+    assert np.all(ss >= sc)
+    occ = float(sc[1]) / float(ss[1])   # adaptive windows
+    assert 0.2 < occ <= 1.0, occ

@@ -130,3 +130,18 @@ def test_overlap_on_device(xd, wl):
         overlapped = time.perf_counter() - t0
     note(f"4 batches: serial {serial * 1e3:.1f} ms, overlapped {overlapped * 1e3:.1f} ms")
     assert overlapped < serial
+
+
+def test_sub_batch_hand_off_equals_whole(xd, wl):
+    """A producer batch handed over as sub-batches (submitted back to back,
+    waited together) gives the same results as the whole batch."""
+    recs = wl.records[5000:17000]
+    note("12,000 records whole vs 5 sub-batches of 2,500 (last 2,000)")
+    with xd.Context(wl.store, max_inflight=4) as ctx:
+        whole, cw, _ = ctx.run(recs, count_cells=True)
+        parts = [ctx.submit(recs[o:o + 2500], count_cells=True) for o in range(0, len(recs), 2500)]
+        for t, _, _ in parts:
+            ctx.wait(t)
+    split = np.concatenate([p[1] for p in parts])
+    cs = np.concatenate([p[2] for p in parts])
+    assert np.array_equal(whole, split) and np.array_equal(cw, cs)
