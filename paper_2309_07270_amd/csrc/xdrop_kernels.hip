@@ -427,7 +427,7 @@ struct Window {
     // (bit per lane).
     template <bool ODD, bool BOUNDS, int KU = -1>
     __device__ __forceinline__ uint64_t step(XState &s, int d, uint32_t ub_rt, int &tp, int &ti, int sm, int nd,
-                                             int G, int X, int m, int n)
+                                             int G, int X, int lo_s = 0, int hi_s = 0)
     {
         // KU >= 0: the pair offset is the compile-time constant KU (unrolled loop)
         const uint32_t ub = KU >= 0 ? (uint32_t)KU : ub_rt;
@@ -448,14 +448,7 @@ struct Window {
             for (int r = 0; r < C - 1; ++r) t[r] = max(Z1[r], Z1[r + 1]);
             t[C - 1] = max(__builtin_amdgcn_mov_dpp(Z1[0], 0x134, 0xf, 0xf, true), Z1[C - 1]);
         }
-        int lo_s = 0, hi_s = 0;
-        if (BOUNDS) {
-            const int o = s.base + (d >> 1);
-            // only j <= n and i <= m can fail: a cell with i < 0 or j < 0 has
-            // no live predecessor (moves never decrease i or j from (0, 0))
-            lo_s = d - n - o;
-            hi_s = m - o;
-        }
+        // BOUNDS: candidates only in slots lo_s .. hi_s (j <= n, i <= m)
         uint64_t imp = 0, lm[C];
         int v[C];
         if (COUNT) s.slots += (uint64_t)WIN;
@@ -620,8 +613,8 @@ struct Window {
         if constexpr (K == UMAX) {
             return acc;
         } else {
-            step<true, false, 2 * K>(s, d0 + 2 * K, 0u, tp, ti, sm, nd, G, X, m, n);
-            acc |= step<false, false, 2 * K>(s, d0 + 2 * K + 1, 0u, tp, ti, sm, nd, G, X, m, n);
+            step<true, false, 2 * K>(s, d0 + 2 * K, 0u, tp, ti, sm, nd, G, X);
+            acc |= step<false, false, 2 * K>(s, d0 + 2 * K + 1, 0u, tp, ti, sm, nd, G, X);
             return pairs_spec<K + 1>(s, d0, tp, ti, sm, nd, G, X, m, n, acc);
         }
     }
@@ -644,14 +637,33 @@ struct Window {
     __device__ __forceinline__ uint32_t pairs(XState &s, int d0, int np, int &tp, int &ti, int sm, int nd, int G,
                                               int X, int m, int n)
     {
+        // clipping (BOUNDS): only j <= n and i <= m can fail, since a cell
+        // with i < 0 or j < 0 has no live predecessor (moves never decrease
+        // i or j from (0, 0)).  With o = base + floor(d/2) the lowest slot
+        // with j <= n, d - n - o, rises by one per pair at the odd step; the
+        // highest slot with i <= m, m - o, falls by one at the even step.
+        const int o0 = s.base + (d0 >> 1);
+        int lo_s = d0 - n - o0, hi_s = m - o0;
         const uint32_t ube = 2u * (uint32_t)np;
         uint32_t ub = 0;
         do {
-            step<true, BOUNDS>(s, d0 + (int)ub, ub, tp, ti, sm, nd, G, X, m, n);
-            const uint64_t e = step<false, BOUNDS>(s, d0 + (int)ub + 1, ub, tp, ti, sm, nd, G, X, m, n);
+            step<true, BOUNDS>(s, d0 + (int)ub, ub, tp, ti, sm, nd, G, X, lo_s, hi_s);
+            const uint64_t e =
+                step<false, BOUNDS>(s, d0 + (int)ub + 1, ub, tp, ti, sm, nd, G, X, lo_s, hi_s - 1);
+            ++lo_s;
+            --hi_s;
             ub = next_pair(ub, e);
         } while (ub < ube);
         return ub;
+    }
+
+    // some live slot on the last two anti-diagonals
+    __device__ __forceinline__ bool alive() const
+    {
+        int z = NEG;
+#pragma unroll
+        for (int r = 0; r < C; ++r) z = max(z, max(Z1[r], Z2[r]));
+        return ballot(z > NEG_HALF) != 0;
     }
 
     // live slots over the last two anti-diagonals; false when both are dead
@@ -698,6 +710,8 @@ struct Window {
         last_d = -1;
         lu_o = lu_e = -1;
         li_o = li_e = 0;
+        // improvement threshold of s.d in Z units, carried from block to block
+        int ti = s.T + G * s.d;
         while (s.d <= dend) {
             int mn, mx;
             if (!band(mn, mx)) break;                 // two dead anti-diagonals
@@ -706,6 +720,7 @@ struct Window {
                 save(lds);
                 s.mn = mn;
                 s.mx = mx;
+                s.T = ti - G * s.d;
                 return width + 4 > WIN ? kGrow : kShrink;
             }
             // re-centre the band when it starts closer than kRecentre slots to an edge
@@ -746,7 +761,7 @@ struct Window {
                     else { mmo2[r] = fo; mme2[r] = fe; }
                 }
             }
-            int tp = s.T - X + G * d, ti = s.T + G * d;
+            int tp = ti - X;
             const int dlast = d + 2 * P - 1;
             // no clipping needed when every slot that can hold a candidate
             // (0 .. WIN-2) of every anti-diagonal of the block has i <= m and
@@ -762,7 +777,7 @@ struct Window {
             else
                 ub = pairs<true>(s, d, p0, tp, ti, sm, nd, G, X, m, n);
             int u = (int)(ub & 63u) >> 1;
-            if (NH == 2 && ub < 64u && P > UMAX) {
+            if (NH == 2 && ub < 64u && P > UMAX && alive()) {
                 // second half: end cell of the first, then its sigma words
                 resolve(s, d);
                 const int d1 = d + 2 * UMAX;
@@ -783,8 +798,8 @@ struct Window {
                 resolve(s, d);
             }
             s.d = d + 2 * u;
-            s.T = ti - G * s.d;
         }
+        s.T = ti - G * s.d;
         return kDone;
     }
 };
