@@ -759,7 +759,6 @@ xdrop_status xdrop_batch_create(const xdrop_config *cfg, xdrop_ctx **out)
     c->st.reads = c->d_reads;
     c->st.n_reads = nr;
     c->st.max_len = max_len;
-    c->st.max_base = (int64_t)(nwords - 4) * 16 - 48;
     *out = c.release();
     return XDROP_OK;
 }

@@ -79,7 +79,6 @@ struct StoreDev {
     const ReadInfo *reads;
     uint32_t n_reads;
     uint32_t max_len;
-    int64_t max_base;         // largest base index a loader may touch
 };
 
 // Tunable launch parameters (the autotuner picks them).

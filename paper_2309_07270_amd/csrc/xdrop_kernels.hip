@@ -12,19 +12,22 @@
 //   * reads: 2 bits per base, both orientations, in one word array;
 //   * one wavefront runs one extension (task); all control is wave-uniform
 //     and lives in SGPRs;
-//   * window kernel: the live band of three consecutive anti-diagonals is
-//     held in VGPRs, 64 lanes x C cells, indexed by slot s = C*lane + r with
+//   * window kernels: the live band of anti-diagonals d-1 and d-2 is held in
+//     VGPRs, 64 lanes x C cells, indexed by slot s = C*lane + r with
 //     i = o_d + s and o_d = base + floor(d/2).  With that origin the diagonal
 //     predecessor of a cell sits in the same slot two anti-diagonals back and
-//     the two gap predecessors are slots (s, s+1) on even d and (s-1, s) on
-//     odd d, so one DPP wave shift per anti-diagonal feeds the recurrence;
+//     the two gap predecessors are slots (s-1, s) on odd d and (s, s+1) on
+//     even d, so one DPP wave rotate per anti-diagonal feeds the recurrence;
 //   * values are stored as Z = S + |gap| * d, which removes the gap add from
-//     the recurrence; the thresholds move by |gap| per anti-diagonal;
-//   * work proceeds in blocks of U (odd, even) anti-diagonal pairs; between
-//     blocks the band is re-centred, its growth bound (one slot per pair on
-//     each side) guarantees that no candidate leaves the window inside a
-//     block, and a band that no longer fits escalates the task to a wider
-//     class;
+//     the recurrence; the drop and improvement thresholds move by |gap| per
+//     anti-diagonal in SGPRs;
+//   * work proceeds in blocks of up to 32 (odd, even) anti-diagonal pairs per
+//     load of codes, run as halves of 16.  A block starts with the band away
+//     from the window edges (re-centred through LDS if needed) and ends when
+//     the even anti-diagonal of a pair has a live cell in an edge slot, which
+//     keeps every candidate inside the window.  At one cell per lane a half
+//     runs unrolled without tests and is rerun with them if an edge slot went
+//     live.  A band that outgrows the window moves to a wider window or class;
 //   * generic kernel: three anti-diagonals in global memory, any band width.
 #include <hip/hip_runtime.h>
 
@@ -36,7 +39,7 @@ namespace {
 
 constexpr int NEG = -(1 << 30) - (1 << 20);   // dead / outside the table
 constexpr int NEG_HALF = -(1 << 29);          // anything below is "no live predecessor"
-constexpr int UMAX = 16;                      // anti-diagonal pairs per block (max)
+constexpr int UMAX = 16;                      // anti-diagonal pairs per half block
 constexpr int kRecentre = 4;                  // a block starting nearer an edge re-centres the band
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
@@ -362,13 +365,14 @@ struct Window {
     uint32_t mmo[C], mme[C];  // per pair u: mismatch bit (bit 2u) or, SIGF, sigma field (bits 2u..2u+1)
     uint32_t mmo2[C], mme2[C];  // the same for pairs UMAX .. 2*UMAX-1 (NH = 2)
 
-    // deferred end cell (MA1): last improving anti-diagonal of the block, its
-    // improvement mask over lanes and, per lane, the first improving slot r
+    // deferred end cell (MA1, C > 1): last improving anti-diagonal since the
+    // last resolve(), its improvement mask over lanes and, per lane, the
+    // first improving slot r
     int last_d;
     uint64_t last_imp;
     int last_r;
     // C = 1: the same per parity of d (odd / even step of a pair), as the
-    // pair offset 2u of the step (-1: none in this block)
+    // pair offset 2u of the step within its half (-1: none since resolve())
     int lu_o, lu_e;
     uint64_t li_o, li_e;
 
@@ -555,8 +559,8 @@ struct Window {
         return ((lm[0] | lm[1]) & 1ull) | ((lm[C - 2] | lm[C - 1]) & (1ull << 63));
     }
 
-    // end cell of the last improvement recorded in the block that began at d0
-    // (MA1): the later of the last odd and the last even improving step
+    // end cell of the last improvement recorded in the half that began at d0
+    // (MA1): at C = 1 the later of the last odd and the last even improving step
     __device__ __forceinline__ void resolve(XState &s, int d0)
     {
         if (!MA1) return;
@@ -694,7 +698,7 @@ struct Window {
     // anti-diagonal is then live inside [2, WIN-3] and the odd one inside
     // [1, WIN-2]: every candidate lies in the window and the value a rotate
     // wraps around from the far edge slot is dead.
-    __device__ uint32_t run(const uint32_t *__restrict__ W, int64_t maxp, const Geo &g, int X, int ma, int mi,
+    __device__ uint32_t run(const uint32_t *__restrict__ W, const Geo &g, int X, int ma, int mi,
                             int gap, int *lds, XState &s, int shrink_width)
     {
         const int lane = lane_id();
@@ -706,7 +710,6 @@ struct Window {
         const int dend = m + n;
         const uint32_t *aseq = W + (g.abase >> 4), *bseq = W + (g.bbase >> 4);
         const int aph = (int)(g.abase & 15), bph = (int)(g.bbase & 15);
-        (void)maxp;
         last_d = -1;
         lu_o = lu_e = -1;
         li_o = li_e = 0;
@@ -830,7 +833,7 @@ __device__ __forceinline__ int fit_c(int width, int margin)
 // false if the band outgrew the widest window (the task then restarts in the
 // next class).
 template <bool COUNT, bool MA1, bool SIGF>
-__device__ bool run_adaptive(const uint32_t *__restrict__ W, int64_t maxp, const Task &k, int *lds, XState &s,
+__device__ bool run_adaptive(const uint32_t *__restrict__ W, const Task &k, int *lds, XState &s,
                              int grow_margin, int shrink_margin)
 {
     // margins >= 2: a band that was just narrowed fits its new window with
@@ -848,22 +851,22 @@ __device__ bool run_adaptive(const uint32_t *__restrict__ W, int64_t maxp, const
         case 1: {
             Window<1, COUNT, MA1, SIGF> w;
             if (fresh) w.init(s); else w.load(lds, from_win, delta);
-            st = w.run(W, maxp, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
+            st = w.run(W, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
         } break;
         case 2: {
             Window<2, COUNT, MA1, SIGF> w;
             if (fresh) w.init(s); else w.load(lds, from_win, delta);
-            st = w.run(W, maxp, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
+            st = w.run(W, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
         } break;
         case 3: {
             Window<3, COUNT, MA1, SIGF> w;
             if (fresh) w.init(s); else w.load(lds, from_win, delta);
-            st = w.run(W, maxp, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
+            st = w.run(W, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
         } break;
         default: {
             Window<4, COUNT, MA1, SIGF> w;
             if (fresh) w.init(s); else w.load(lds, from_win, delta);
-            st = w.run(W, maxp, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
+            st = w.run(W, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
         } break;
         }
         if (st == kDone) return true;
@@ -901,11 +904,11 @@ __global__ void __launch_bounds__(256) adaptive_kernel(BatchDev b, StoreDev st, 
         XState s;
         bool ok;
         if (k.ma != 1)
-            ok = run_adaptive<COUNT, false, false>(st.words, st.max_base, k, lds, s, grow_margin, shrink_margin);
+            ok = run_adaptive<COUNT, false, false>(st.words, k, lds, s, grow_margin, shrink_margin);
         else if (sigma_fits_2bits(k))
-            ok = run_adaptive<COUNT, true, true>(st.words, st.max_base, k, lds, s, grow_margin, shrink_margin);
+            ok = run_adaptive<COUNT, true, true>(st.words, k, lds, s, grow_margin, shrink_margin);
         else
-            ok = run_adaptive<COUNT, true, false>(st.words, st.max_base, k, lds, s, grow_margin, shrink_margin);
+            ok = run_adaptive<COUNT, true, false>(st.words, k, lds, s, grow_margin, shrink_margin);
         if (ok) {
             TaskOut o;   // every lane stores the same (wave-uniform) values
             o.score = s.T; o.i = s.bi; o.j = s.bj; o.status = (uint32_t)cls; o.cells = s.cells; o.slots = s.slots;
@@ -935,15 +938,15 @@ __global__ void __launch_bounds__(256) wide_kernel(BatchDev b, StoreDev st, int 
         if (k.ma != 1) {
             WideWindow<C, COUNT, false, false> w;
             w.init(s);
-            status = w.run(st.words, st.max_base, k.g, k.x, k.ma, k.mi, k.gap, lds, s, -1);
+            status = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, lds, s, -1);
         } else if (sigma_fits_2bits(k)) {
             WideWindow<C, COUNT, true, true> w;
             w.init(s);
-            status = w.run(st.words, st.max_base, k.g, k.x, k.ma, k.mi, k.gap, lds, s, -1);
+            status = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, lds, s, -1);
         } else {
             WideWindow<C, COUNT, true, false> w;
             w.init(s);
-            status = w.run(st.words, st.max_base, k.g, k.x, k.ma, k.mi, k.gap, lds, s, -1);
+            status = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, lds, s, -1);
         }
         if (status == kDone) {
             TaskOut o;
