@@ -141,7 +141,7 @@ struct xdrop_ctx {
     Tuning tune{};
     std::string tuning_path;
 
-    std::mutex mu;
+    mutable std::mutex mu;
     std::condition_variable cv;
     std::vector<std::unique_ptr<Slot>> slots;
     std::unordered_map<uint64_t, std::shared_ptr<Ticket>> tickets;
@@ -836,6 +836,7 @@ xdrop_status xdrop_batch_wait(xdrop_ctx *c, xdrop_ticket id, int64_t timeout_us,
 xdrop_status xdrop_get_tuning(const xdrop_ctx *c, xdrop_tuning *out)
 {
     if (!c || !out) return XDROP_E_INVALID;
+    std::lock_guard<std::mutex> lk(c->mu);   // set_tuning / autotune write under the same lock
     out->grow_margin = c->tune.grow_margin;
     out->shrink_margin = c->tune.shrink_margin;
     out->waves_per_cu = c->tune.waves_per_cu;

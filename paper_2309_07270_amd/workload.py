@@ -142,10 +142,13 @@ def overlapping_pairs(start: np.ndarray, end: np.ndarray, min_overlap: int = 500
     return order[i_idx[keep]], order[j_idx[keep]]
 
 
-def _apply_errors(rng, genome, t_start, t_len, protect_off, protect_read, k, chunk=1 << 24):
-    """Apply the 8/4/3 % error mix to every template; returns forward-frame reads
-    (concatenated), their offsets/lengths and, for each protected k-mer, its
-    position in its read's forward frame."""
+def _apply_errors(rng, genome, t_start, t_len, protect_off, protect_read, k, chunk=1 << 24,
+                  rates=(0.08, 0.04, 0.03)):
+    """Apply the substitution / insertion / deletion mix (default 8/4/3 %) to
+    every template; returns forward-frame reads (concatenated), their
+    offsets/lengths and, for each protected k-mer, its position in its read's
+    forward frame."""
+    p_sub, p_ins, p_del = rates
     n = t_len.size
     out_parts, out_len = [], np.zeros(n, np.int64)
     prot_pos = np.zeros(protect_off.size, np.int64)
@@ -173,9 +176,9 @@ def _apply_errors(rng, genome, t_start, t_len, protect_off, protect_read, k, chu
             np.add.at(diff, g0 + k, -1)
         prot = np.cumsum(diff[:-1]) > 0
         u = rng.random(tot)
-        sub = (u < 0.08) & ~prot
-        ins = (u >= 0.08) & (u < 0.12) & ~prot
-        dele = (u >= 0.12) & (u < 0.15) & ~prot
+        sub = (u < p_sub) & ~prot
+        ins = (u >= p_sub) & (u < p_sub + p_ins) & ~prot
+        dele = (u >= p_sub + p_ins) & (u < p_sub + p_ins + p_del) & ~prot
         base = tmpl.copy()
         base[sub] = (base[sub] + rng.integers(1, 4, size=int(sub.sum()))) % 4
         cnt = np.ones(tot, np.int64) + ins - dele
@@ -321,3 +324,32 @@ def random_store(rng, n_reads: int, lo: int, hi: int, related: float = 0.5) -> R
     codes = np.concatenate(parts) if parts else np.zeros(0, np.uint8)
     off = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
     return ReadStore(codes, off, lens.astype(np.int64))
+
+
+def make_readset(name: str = "c1", error: float = 0.01, seed: int | None = None, genome: int | None = None,
+                 coverage: float | None = None) -> ReadStore:
+    """Reads only (no records), for seed discovery: the preset's genome size,
+    coverage and length law, strands +/- with p = 1/2 ('-' stored reverse-
+    complemented), and a total error rate split 8:4:3 into substitutions,
+    insertions and deletions.  A shared 31-mer survives in ~(1-error)^31 of
+    the reads that cover it, so the paper's frequency windows ([20, 30] at
+    29x, [20, 50] at 100x) only select k-mers of near error-free reads."""
+    p = PRESETS[name]
+    if seed is None:
+        seed = SEED_BASE + 100 + PRESET_INDEX[name]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    G = genome or p.genome
+    cov = coverage or p.coverage
+    gen = rng.integers(0, 4, size=G, dtype=np.uint8)
+    mean_len = p.len_a if p.length_law == "lognormal" else (p.len_a + p.len_b) / 2
+    n_reads = max(2, int(round(cov * G / mean_len)))
+    t_len = np.minimum(_lengths(rng, p, n_reads), G)
+    t_start = (rng.random(n_reads) * (G - t_len + 1)).astype(np.int64)
+    t_strand = rng.integers(0, 2, size=n_reads).astype(np.int64)
+    rates = (error * 8 / 15, error * 4 / 15, error * 3 / 15)
+    codes, off, length, _ = _apply_errors(rng, gen, t_start, t_len, np.zeros(0, np.int64),
+                                          np.zeros(0, np.int64), 1, rates=rates)
+    for r in np.flatnonzero(t_strand == 1):
+        o, ln = int(off[r]), int(length[r])
+        codes[o:o + ln] = revcomp_codes(codes[o:o + ln])
+    return ReadStore(codes, off, length)
