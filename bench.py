@@ -97,6 +97,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=6.0)
     ap.add_argument("--serve-points", default="0.1,0.3,0.5,0.7,0.9,1.0,1.1,1.2")
     ap.add_argument("--producers", type=int, default=25)
+    ap.add_argument("--seeds", action="store_true",
+                    help="seed discovery on a c1-shaped 1%%-error read set (k=31, stride 1, window [20, 30]), "
+                         "then the X-drop batch over the seeds found (X=15)")
     ap.add_argument("--granularity", default="0",
                     help="serving hand-off granularity ablation: comma list of sub-batch sizes "
                          "(0 = whole batch); each producer batch is split into sub-batches "
@@ -128,6 +131,9 @@ def main():
 
     if args.serve:
         serve_main(args)
+        return
+    if args.seeds:
+        seeds_main(args)
         return
 
     t0 = time.time()
@@ -303,6 +309,62 @@ def main():
         log(f"cpu oracle, 1 thread: {cells1 / c1_el / 1e9:.3f} GCUPS")
 
     print(json.dumps(out))
+
+
+def seeds_main(args):
+    """Seed discovery (the step before the batches) and seed-and-extend of the
+    seeds it finds.  Reads: 29x of a 4.6 Mb genome, c1 length law, 1 % error
+    (the paper's frequency window [20, 30] at 29x keeps only k-mers of near
+    error-free reads); k = 31, stride 1, window [20, 30] and X = 15 as in the
+    paper's runs ("Method")."""
+    import numpy as np
+    import torch
+
+    from paper_2309_07270_amd import workload as W
+    from paper_2309_07270_amd import xdrop as X
+
+    t0 = time.time()
+    st = W.make_readset("c1", error=0.01)
+    log(f"read set: {st.n} reads, {int(st.length.sum())} bases, gen {time.time() - t0:.1f}s")
+    ctx = X.Context(st)
+    recs, s0 = ctx.find_seeds(k=31, lo=20, hi=30, x=15)          # warm-up and sizing
+    ms = []
+    for _ in range(max(args.steps // 4, 3)):
+        r2, s1 = ctx.find_seeds(k=31, lo=20, hi=30, x=15, max_records=len(recs))
+        ms.append(s1["device_ms"])
+    assert len(r2) == len(recs)
+    dev_ms = float(np.median(ms))
+    log(f"seeds: {s0['kmers']} k-mers, {s0['distinct']} distinct, {s0['reliable']} reliable, "
+        f"{len(recs)} pairs in {dev_ms:.2f} ms")
+    # seed-and-extend of the pairs found, persistent form, records in HBM
+    n = len(recs)
+    d_recs = torch.from_numpy(recs.view(np.uint8).copy()).cuda()
+    d_out = torch.zeros(n * 32, dtype=torch.uint8, device="cuda")
+    d_cells = torch.zeros(n, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    ctx.wait(ctx.submit_device(d_recs, n, d_out, d_cells, stream=stream))
+    torch.cuda.synchronize()
+    cells = int(d_cells.cpu().numpy().sum())
+    t1 = time.perf_counter()
+    steps = args.steps
+    for _ in range(steps):
+        ctx.wait(ctx.submit_device(d_recs, n, d_out, None, stream=stream))
+    torch.cuda.synchronize()
+    ext_ms = (time.perf_counter() - t1) * 1e3 / steps
+    res = d_out.cpu().numpy().view(W.RESULT_DTYPE)
+    ctx.close()
+    log(f"extension of the seeds: {ext_ms:.2f} ms per batch, {cells / ext_ms / 1e6:.1f} GCUPS")
+    print(json.dumps({
+        "metric": "seed discovery (k-mers/s, pairs/s) and seed-and-extend of the pairs found (GCUPS) on 1 GPU",
+        "data": "synthetic: 29x of a 4.6 Mb genome, lognormal mean 8 kb reads, 1 % error (8:4:3 sub:ins:del)",
+        "params": {"k": 31, "stride": 1, "lo": 20, "hi": 30, "x": 15, "weights": [1, -1, -1]},
+        "reads": int(st.n), "bases": int(st.length.sum()),
+        "seeds": {"kmers": int(s0["kmers"]), "distinct": int(s0["distinct"]), "reliable": int(s0["reliable"]),
+                  "pairs": n, "device_ms": round(dev_ms, 3),
+                  "kmers_per_s": round(s0["kmers"] / dev_ms * 1e3, 1), "pairs_per_s": round(n / dev_ms * 1e3, 1)},
+        "extension": {"records": n, "cells": cells, "ms_per_batch": round(ext_ms, 3),
+                      "gcups": round(cells / ext_ms / 1e6, 2),
+                      "mean_score": round(float(res["score"].mean()), 1) if n else None}}))
 
 
 def serve_main(args):

@@ -203,6 +203,54 @@ xdrop_status xdrop_autotune(xdrop_ctx *c, const xdrop_record *recs, size_t n, co
  * including the unbounded kernel's scratch).  0 for a NULL context. */
 uint64_t xdrop_batch_footprint(const xdrop_ctx *c, size_t n);
 
+/* ---- Seed discovery (the step before the batches) ------------------------
+ * Records for the read pairs of the context's store that share a reliable
+ * k-mer (paper, "Related works": BELLA detects overlaps from shared k-mers
+ * after filtering unreliable ones, then extends the seeds with an X-drop;
+ * "Method": k-mer length 31, stride 1, frequency window [20, 30] for the 29x
+ * data set and [20, 50] for the 100x one):
+ *   - each read contributes the k-mers starting at positions 0, s, 2s, ...;
+ *   - a k-mer and its reverse complement are one k-mer, represented by the
+ *     lexicographically smaller string (A < C < G < T);
+ *   - its frequency is its number of occurrences over all reads and
+ *     positions; it is reliable when lo <= frequency <= hi;
+ *   - two different reads a < b sharing a reliable k-mer give one record:
+ *     every pair of occurrences is a candidate seed (pos_a, pos_b, strand)
+ *     with strand 1 when the two occurrences have opposite orientations, and
+ *     the record takes the smallest candidate in (pos_a, pos_b, strand)
+ *     order; positions are in the reads' stored coordinates, as everywhere
+ *     in xdrop_record, so the seed is exact in A against B'.
+ * k, x and the weights are copied into every record.  */
+typedef struct {
+    uint32_t k;                   /* 1..31                                    */
+    uint32_t stride;              /* >= 1                                     */
+    uint32_t lo, hi;              /* frequency window, 1 <= lo <= hi <= 4096  */
+    int32_t x;                    /* X-drop of the records (0..2^30)          */
+    int16_t match, mismatch, gap; /* weights of the records (record rules)    */
+    int16_t pad;
+} xdrop_seed_params;
+
+typedef struct {
+    uint64_t kmers;               /* k-mer occurrences counted                */
+    uint64_t distinct;            /* distinct canonical k-mers                */
+    uint64_t reliable;            /* canonical k-mers inside [lo, hi]         */
+    uint64_t pairs;               /* read pairs found                         */
+    double device_ms;             /* kernels, first to last                   */
+} xdrop_seed_stats;
+
+/* Find the seed records of the whole store.  out receives min(pairs,
+ * max_records) records in unspecified order; it is host memory, or device
+ * memory of the context's GPU when out_on_device != 0 (out may be NULL when
+ * max_records = 0).  *n_found gets the number of pairs.  Returns
+ * XDROP_E_INVALID for bad parameters, XDROP_E_NOMEM when out is too small
+ * (*n_found then says how many records are needed; the records written are
+ * a subset) or device memory runs out.  Scratch (about 16 B per k-mer plus
+ * 8 B per occurrence slot of the reliable k-mers) is allocated per call,
+ * outside the HBM budget of the batches, and freed before returning.  May
+ * run concurrently with batches on the same context. */
+xdrop_status xdrop_find_seeds(xdrop_ctx *c, const xdrop_seed_params *p, xdrop_record *out, size_t max_records,
+                              int out_on_device, size_t *n_found, xdrop_seed_stats *stats);
+
 /* Human-readable text of a status code (static storage). */
 const char *xdrop_status_string(xdrop_status s);
 

@@ -7,7 +7,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", "xdrop_kernels.hip"), os.path.join(HERE, "csrc", "xdrop_capi.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", "xdrop_kernels.hip"), os.path.join(HERE, "csrc", "seed_kernels.hip"),
+           os.path.join(HERE, "csrc", "xdrop_capi.cpp")]
 LIB = os.path.join(HERE, "libxdrop.so")
 # measuring tool (int32 VALU peak of the GPU), loaded only by bench.py
 PROBE_SOURCES = [os.path.join(HERE, "csrc", "valu_probe.hip")]

@@ -973,4 +973,94 @@ xdrop_status xdrop_batch_destroy(xdrop_ctx *c)
     return XDROP_OK;
 }
 
+xdrop_status xdrop_find_seeds(xdrop_ctx *c, const xdrop_seed_params *p, xdrop_record *out, size_t max_records,
+                              int out_on_device, size_t *n_found, xdrop_seed_stats *stats)
+{
+    if (!c || !p || !n_found || (max_records && !out)) return XDROP_E_INVALID;
+    if (p->k < 1 || p->k > 31 || p->stride < 1 || p->lo < 1 || p->lo > p->hi || p->hi > 4096 || p->x < 0 ||
+        p->x > XDROP_MAX_X || p->match < 1 || p->match > 1024 || p->mismatch >= p->match || p->mismatch < -1024 ||
+        p->gap > -1 || p->gap < -1024 || max_records > 0xffffffffu) {
+        c->fail("xdrop_find_seeds: bad parameters");
+        return XDROP_E_INVALID;
+    }
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        if (c->poisoned) return XDROP_E_DEVICE;
+    }
+    uint64_t kmers = 0;
+    for (uint32_t len : c->h_len)
+        if (len >= p->k) kmers += (len - p->k) / p->stride + 1;
+    auto pow2 = [](uint64_t v) { uint64_t r = 1024; while (r < v) r <<= 1; return r; };
+    SeedDev sd{};
+    sd.k = (int)p->k; sd.stride = (int)p->stride; sd.lo = (int)p->lo; sd.hi = (int)p->hi;
+    sd.cap = pow2(2 * kmers);                       // load factor <= 1/2
+    sd.max_reliable = (uint32_t)std::min<uint64_t>(kmers / p->lo + 1, 0xffffffffu);
+    sd.pcap = pow2(2 * (uint64_t)max_records);
+    std::vector<void *> bufs;
+    hipStream_t s = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    auto release = [&]() {
+        if (s) hipStreamSynchronize(s);
+        for (void *b : bufs) hipFree(b);
+        for (auto e : ev) if (e) hipEventDestroy(e);
+        if (s) hipStreamDestroy(s);
+    };
+    try {
+        HIP_TRY(hipSetDevice(c->device));
+        auto dalloc = [&](size_t bytes) {
+            void *ptr = nullptr;
+            if (hipMalloc(&ptr, std::max<size_t>(bytes, 256)) != hipSuccess) {
+                (void)hipGetLastError();
+                throw std::bad_alloc();
+            }
+            bufs.push_back(ptr);
+            return ptr;
+        };
+        sd.keys = (uint64_t *)dalloc(sd.cap * 8);
+        sd.counts = (uint32_t *)dalloc(sd.cap * 4);
+        sd.rid = (int32_t *)dalloc(sd.cap * 4);
+        sd.fill = (uint32_t *)dalloc((size_t)sd.max_reliable * 4);
+        sd.occ = (uint64_t *)dalloc((size_t)sd.max_reliable * p->hi * 8);
+        sd.pkeys = (uint64_t *)dalloc(sd.pcap * 8);
+        sd.pvals = (uint64_t *)dalloc(sd.pcap * 8);
+        sd.ctr = (uint32_t *)dalloc(kSeedCounters * 4);
+        xdrop_record *d_out = out_on_device ? out : (xdrop_record *)dalloc(max_records * sizeof(xdrop_record));
+        HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreate(&ev[0]));
+        HIP_TRY(hipEventCreate(&ev[1]));
+        launch_seeds(sd, c->st, d_out, (uint32_t)max_records, p->x, p->match, p->mismatch, p->gap, c->cus, s, ev);
+        HIP_TRY(hipGetLastError());
+        uint32_t ctr[kSeedCounters] = {};
+        HIP_TRY(hipMemcpyAsync(ctr, sd.ctr, sizeof(ctr), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const size_t written = std::min<size_t>(ctr[kSeedPairs], max_records);
+        if (!out_on_device && written)
+            HIP_TRY(hipMemcpy(out, d_out, written * sizeof(xdrop_record), hipMemcpyDeviceToHost));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        *n_found = ctr[kSeedPairs];
+        if (stats) {
+            stats->kmers = kmers;
+            stats->distinct = ctr[kSeedDistinct];
+            stats->reliable = ctr[kSeedReliable];
+            stats->pairs = ctr[kSeedPairs];
+            stats->device_ms = ms;
+        }
+        release();
+        if (ctr[kSeedOverflow] || ctr[kSeedPairs] > max_records) {
+            c->fail("xdrop_find_seeds: more read pairs than max_records");
+            return XDROP_E_NOMEM;
+        }
+        return XDROP_OK;
+    } catch (const std::bad_alloc &) {
+        release();
+        c->fail("xdrop_find_seeds: device memory");
+        return XDROP_E_NOMEM;
+    } catch (const std::exception &e) {
+        release();
+        c->fail(e.what());
+        return XDROP_E_DEVICE;
+    }
+}
+
 }  // extern "C"

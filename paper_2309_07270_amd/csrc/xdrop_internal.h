@@ -105,4 +105,26 @@ void launch_generic(const BatchDev &b, const StoreDev &st, int32_t *scratch, uin
                     uint32_t grid_waves, bool count_cells, hipStream_t s);
 void launch_finalize(const BatchDev &b, const StoreDev &st, uint32_t n, bool stage_sums, hipStream_t s);
 
+// Seed discovery: device tables of one call (see seed_kernels.hip).
+enum : int { kSeedOverflow = 0, kSeedDistinct = 1, kSeedReliable = 2, kSeedPairs = 3, kSeedCounters = 4 };
+struct SeedDev {
+    uint64_t *keys;           // k-mer table: canonical code, ~0 = empty
+    uint32_t *counts;         //   occurrences of the entry
+    int32_t *rid;             //   index among the reliable k-mers, -1 if not reliable
+    uint64_t cap;             //   slots (power of two)
+    uint32_t *fill;           // per reliable k-mer: occurrences stored
+    uint64_t *occ;            // per reliable k-mer: hi slots of (read << 32 | pos << 1 | reverse)
+    uint32_t max_reliable;    // reliable k-mers the buffers hold
+    uint64_t *pkeys;          // pair table: read_a << 32 | read_b, ~0 = empty
+    uint64_t *pvals;          //   smallest pos_a << 32 | pos_b << 1 | strand
+    uint64_t pcap;            //   slots (power of two)
+    uint32_t *ctr;            // kSeedCounters counters
+    int k, stride, lo, hi;
+};
+
+// init, count, reliable, occurrences, pairs, emit; ev[0] / ev[1] (nullable)
+// are recorded after init and after emit
+void launch_seeds(const SeedDev &sd, const StoreDev &st, xdrop_record *d_out, uint32_t max_out, int x, int ma,
+                  int mi, int gap, int cus, hipStream_t s, hipEvent_t *ev);
+
 }  // namespace xd

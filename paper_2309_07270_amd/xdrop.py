@@ -58,6 +58,20 @@ class Stats(ctypes.Structure):
         return out
 
 
+class SeedParams(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("stride", ctypes.c_uint32), ("lo", ctypes.c_uint32),
+                ("hi", ctypes.c_uint32), ("x", ctypes.c_int32), ("match", ctypes.c_int16),
+                ("mismatch", ctypes.c_int16), ("gap", ctypes.c_int16), ("pad", ctypes.c_int16)]
+
+
+class SeedStats(ctypes.Structure):
+    _fields_ = [("kmers", ctypes.c_uint64), ("distinct", ctypes.c_uint64), ("reliable", ctypes.c_uint64),
+                ("pairs", ctypes.c_uint64), ("device_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("grow_margin", ctypes.c_int32), ("shrink_margin", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("buckets", ctypes.c_int32),
@@ -100,6 +114,8 @@ def load_library(path: str = LIB_PATH):
     lib.xdrop_get_tuning.argtypes = [vp, P(Tuning)]
     lib.xdrop_set_tuning.argtypes = [vp, P(Tuning)]
     lib.xdrop_autotune.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_char_p, P(ctypes.c_double)]
+    lib.xdrop_find_seeds.argtypes = [vp, P(SeedParams), vp, ctypes.c_size_t, ctypes.c_int, P(ctypes.c_size_t),
+                                     P(SeedStats)]
     for f in ("xdrop_get_tuning", "xdrop_set_tuning", "xdrop_autotune"):
         getattr(lib, f).restype = ctypes.c_int
     for f in ("xdrop_batch_create", "xdrop_batch_submit", "xdrop_batch_submit_device", "xdrop_batch_wait",
@@ -182,6 +198,27 @@ class Context:
         self._check(self.lib.xdrop_autotune(self.h, _ptr(recs), recs.size,
                                             cache_path.encode() if cache_path else None, ctypes.byref(best)))
         return self.tuning(), best.value
+
+    def find_seeds(self, k: int = 31, stride: int = 1, lo: int = 20, hi: int = 30, x: int = 15,
+                   weights=(1, -1, -1), max_records: int | None = None):
+        """Seed records of the read pairs sharing a reliable k-mer (host array,
+        order unspecified) and the call's statistics.  Without max_records the
+        output starts at 64 records per read and grows once to the exact count."""
+        ma, mi, g = weights
+        prm = SeedParams(k, stride, lo, hi, x, ma, mi, g, 0)
+        cap = max_records if max_records is not None else max(1024, 64 * self.n_reads)
+        for _ in range(2):
+            out = np.zeros(cap, RECORD_DTYPE)
+            found = ctypes.c_size_t()
+            st = SeedStats()
+            rc = self.lib.xdrop_find_seeds(self.h, ctypes.byref(prm), _ptr(out) if cap else None, cap, 0,
+                                           ctypes.byref(found), ctypes.byref(st))
+            if rc == XDROP_E_NOMEM and max_records is None and found.value > cap:
+                cap = found.value
+                continue
+            self._check(rc)
+            return out[:found.value], st.as_dict()
+        self._check(rc)
 
     def error(self) -> str:
         return self.lib.xdrop_last_error(self.h).decode()
