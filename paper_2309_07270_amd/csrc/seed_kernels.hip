@@ -13,7 +13,8 @@
 // Pipeline, with no sort:
 //   1. count: every k-mer of every read into an open-addressing table
 //      (64-bit compare-and-swap on the key, linear probing);
-//   2. reliable: each entry with lo <= count <= hi gets an index;
+//   2. reliable: each entry with lo <= count <= hi gets a dense index
+//      (per-wavefront counts over table chunks, a scan, an assignment);
 //   3. occurrences: each occurrence of a reliable k-mer is appended to the
 //      k-mer's list (hi slots per reliable k-mer);
 //   4. pairs: every two occurrences of one list from different reads give a
@@ -65,19 +66,31 @@ __device__ __forceinline__ uint64_t canonical_at(const uint32_t *__restrict__ W,
     return rev ? rc : fwd;
 }
 
-// table slot holding `key`, inserting it if absent; -1 if the table is full
+// table slot holding `key`, inserting it if absent (insert) or -1 if absent
+// (lookup); -1 if the table is full.  A key already present is found by a
+// plain load; the compare-and-swap is only tried on an empty slot.
 __device__ __forceinline__ int64_t slot_of(uint64_t *keys, uint64_t cap, uint64_t key, bool insert)
 {
     uint64_t h = mix64(key) & (cap - 1);
     for (uint64_t probe = 0; probe < cap; ++probe) {
-        const uint64_t cur = insert ? atomicCAS((unsigned long long *)&keys[h], (unsigned long long)kEmpty,
-                                                (unsigned long long)key)
-                                    : keys[h];
-        if (cur == key || (insert && cur == kEmpty)) return (int64_t)h;
-        if (!insert && cur == kEmpty) return -1;
+        uint64_t cur = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
+        if (cur == kEmpty) {
+            if (!insert) return -1;
+            cur = atomicCAS((unsigned long long *)&keys[h], (unsigned long long)kEmpty, (unsigned long long)key);
+            if (cur == kEmpty) return (int64_t)h;
+        }
+        if (cur == key) return (int64_t)h;
         h = (h + 1) & (cap - 1);
     }
     return -1;
+}
+
+// Wave-uniform fetch-and-add of `v` (the value of lane 0); every lane takes
+// part so that no lane-dependent branch surrounds the atomic.
+__device__ __forceinline__ uint32_t wave_fetch_add(uint32_t *p, uint32_t v)
+{
+    const uint32_t old = atomicAdd(p, (threadIdx.x & 63) == 0 ? v : 0u);
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)old);
 }
 
 // positions of read r that start a k-mer: 0, s, 2s, ...
@@ -104,21 +117,81 @@ __global__ void __launch_bounds__(256) kmer_count_kernel(SeedDev sd, StoreDev st
     }
 }
 
-__global__ void __launch_bounds__(256) kmer_reliable_kernel(SeedDev sd)
+// Reliable k-mers get dense indices in two passes over contiguous chunks of
+// the table, one chunk per wavefront: count, exclusive scan over the chunks,
+// assign.  One global atomic per wavefront in all (a counter per entry would
+// serialise on one address).
+__device__ __forceinline__ void chunk_of(const SeedDev &sd, uint32_t wave, uint64_t &h0, uint64_t &h1)
 {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t h = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; h < sd.cap; h += stride) {
-        int32_t rid = -1;
-        if (sd.keys[h] != kEmpty) {
-            atomicAdd(&sd.ctr[kSeedDistinct], 1u);
-            const uint32_t c = sd.counts[h];
-            if (c >= (uint32_t)sd.lo && c <= (uint32_t)sd.hi) {
-                const uint32_t id = atomicAdd(&sd.ctr[kSeedReliable], 1u);
-                if (id < sd.max_reliable) rid = (int32_t)id;
-                else atomicOr(&sd.ctr[kSeedOverflow], 2u);
-            }
-        }
-        sd.rid[h] = rid;
+    h0 = min((uint64_t)wave * sd.chunk, sd.cap);
+    h1 = min(h0 + sd.chunk, sd.cap);
+}
+
+__device__ __forceinline__ bool reliable_at(const SeedDev &sd, uint64_t h, bool &used)
+{
+    used = sd.keys[h] != kEmpty;
+    const uint32_t c = used ? sd.counts[h] : 0u;
+    return used && c >= (uint32_t)sd.lo && c <= (uint32_t)sd.hi;
+}
+
+__global__ void __launch_bounds__(256) kmer_reliable_count_kernel(SeedDev sd)
+{
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t lane = threadIdx.x & 63;
+    uint64_t h0, h1;
+    chunk_of(sd, wave, h0, h1);
+    uint32_t n_used = 0, n_rel = 0;
+    for (uint64_t h = h0 + lane; h < h1; h += 64) {       // chunk: a multiple of 64 slots
+        bool used;
+        const bool rel = reliable_at(sd, h, used);
+        n_used += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(used));
+        n_rel += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(rel));
+    }
+    wave_fetch_add(&sd.ctr[kSeedDistinct], n_used);
+    sd.wcount[wave] = n_rel;   // every lane stores the same (wave-uniform) value
+}
+
+// exclusive scan of n values in one block of 1024 threads; the total goes
+// to *total
+__global__ void __launch_bounds__(1024) scan_kernel(uint32_t *v, uint32_t n, uint32_t *total)
+{
+    __shared__ uint32_t part[1024];
+    const uint32_t t = threadIdx.x;
+    const uint32_t per = (n + 1023) / 1024;
+    const uint32_t b = t * per, e = min(b + per, n);
+    uint32_t sum = 0;
+    for (uint32_t i = b; i < e; ++i) sum += v[i];
+    part[t] = sum;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024; off <<= 1) {      // inclusive Hillis-Steele scan
+        const uint32_t x = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - sum;
+    for (uint32_t i = b; i < e; ++i) {
+        const uint32_t x = v[i];
+        v[i] = run;
+        run += x;
+    }
+    if (t == 1023) *total = part[1023];
+}
+
+__global__ void __launch_bounds__(256) kmer_reliable_assign_kernel(SeedDev sd)
+{
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t lane = threadIdx.x & 63;
+    uint64_t h0, h1;
+    chunk_of(sd, wave, h0, h1);
+    uint32_t next = h0 < h1 ? sd.wcount[wave] : 0u;
+    for (uint64_t h = h0 + lane; h < h1; h += 64) {
+        bool used;
+        const bool rel = reliable_at(sd, h, used);
+        const uint64_t rm = __builtin_amdgcn_ballot_w64(rel);
+        const uint32_t id = next + (uint32_t)__builtin_popcountll(rm & ((1ull << lane) - 1ull));
+        next += (uint32_t)__builtin_popcountll(rm);
+        sd.rid[h] = (rel && id < sd.max_reliable) ? (int32_t)id : -1;
     }
 }
 
@@ -168,8 +241,14 @@ __global__ void __launch_bounds__(256) seed_pair_kernel(SeedDev sd)
             const uint64_t cand = (pa << 32) | (pb << 1) | strand;
             const uint64_t pkey = ((a >> 32) << 32) | (b >> 32);
             const int64_t h = slot_of(sd.pkeys, sd.pcap, pkey, true);
-            if (h >= 0) atomicMin((unsigned long long *)&sd.pvals[h], (unsigned long long)cand);
-            else atomicOr(&sd.ctr[kSeedOverflow], 4u);
+            if (h < 0) {
+                atomicOr(&sd.ctr[kSeedOverflow], 4u);
+                continue;
+            }
+            // stored values only decrease: a candidate not below a (possibly
+            // stale) stored value cannot be the minimum
+            if (cand < __atomic_load_n(&sd.pvals[h], __ATOMIC_RELAXED))
+                atomicMin((unsigned long long *)&sd.pvals[h], (unsigned long long)cand);
         }
     }
 }
@@ -224,7 +303,9 @@ void launch_seeds(const SeedDev &sd, const StoreDev &st, xdrop_record *d_out, ui
     hipLaunchKernelGGL(seed_init_kernel, dim3(blocks), dim3(256), 0, s, sd);
     if (ev) hipEventRecord(ev[0], s);
     hipLaunchKernelGGL(kmer_count_kernel, dim3(blocks), dim3(256), 0, s, sd, st);
-    hipLaunchKernelGGL(kmer_reliable_kernel, dim3(blocks), dim3(256), 0, s, sd);
+    hipLaunchKernelGGL(kmer_reliable_count_kernel, dim3(blocks), dim3(256), 0, s, sd);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, sd.wcount, sd.n_chunks, sd.ctr + kSeedReliable);
+    hipLaunchKernelGGL(kmer_reliable_assign_kernel, dim3(blocks), dim3(256), 0, s, sd);
     hipLaunchKernelGGL(kmer_occurrence_kernel, dim3(blocks), dim3(256), 0, s, sd, st);
     hipLaunchKernelGGL(seed_pair_kernel, dim3(blocks), dim3(256), 0, s, sd);
     hipLaunchKernelGGL(seed_emit_kernel, dim3(blocks), dim3(256), 0, s, sd, d_out, max_out, x, ma, mi, gap);

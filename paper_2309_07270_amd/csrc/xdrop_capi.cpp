@@ -1024,6 +1024,9 @@ xdrop_status xdrop_find_seeds(xdrop_ctx *c, const xdrop_seed_params *p, xdrop_re
         sd.pkeys = (uint64_t *)dalloc(sd.pcap * 8);
         sd.pvals = (uint64_t *)dalloc(sd.pcap * 8);
         sd.ctr = (uint32_t *)dalloc(kSeedCounters * 4);
+        sd.n_chunks = (uint32_t)c->cus * 8u * 4u;                 // wavefronts of the reliable passes
+        sd.chunk = ((sd.cap + sd.n_chunks - 1) / sd.n_chunks + 63) / 64 * 64;
+        sd.wcount = (uint32_t *)dalloc((size_t)sd.n_chunks * 4);
         xdrop_record *d_out = out_on_device ? out : (xdrop_record *)dalloc(max_records * sizeof(xdrop_record));
         HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
         HIP_TRY(hipEventCreate(&ev[0]));

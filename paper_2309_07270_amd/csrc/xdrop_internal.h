@@ -119,10 +119,15 @@ struct SeedDev {
     uint64_t *pvals;          //   smallest pos_a << 32 | pos_b << 1 | strand
     uint64_t pcap;            //   slots (power of two)
     uint32_t *ctr;            // kSeedCounters counters
+    uint32_t *wcount;         // per table chunk: reliable entries, then their first index
+    uint64_t chunk;           // table slots per chunk (a multiple of 64)
+    uint32_t n_chunks;        // chunks = wavefronts of the reliable passes
     int k, stride, lo, hi;
 };
 
-// init, count, reliable, occurrences, pairs, emit; ev[0] / ev[1] (nullable)
+// init, count, reliable (count, scan, assign), occurrences, pairs, emit;
+// sd.n_chunks must equal the wavefronts of cus * 8 blocks of 256 threads and
+// sd.chunk * n_chunks >= sd.cap; ev[0] / ev[1] (nullable)
 // are recorded after init and after emit
 void launch_seeds(const SeedDev &sd, const StoreDev &st, xdrop_record *d_out, uint32_t max_out, int x, int ma,
                   int mi, int gap, int cus, hipStream_t s, hipEvent_t *ev);
