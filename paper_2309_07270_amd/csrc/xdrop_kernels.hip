@@ -888,8 +888,10 @@ __device__ bool run_adaptive(const uint32_t *__restrict__ W, const Task &k, int 
 }
 
 // Class 0: adaptive windows.  Tasks whose band outgrows 256 cells go to class 1.
+// Registers capped for 6 wavefronts per SIMD (the compiler's own choice
+// allows 5; the cap costs one spill at entry and its reload per task).
 template <bool COUNT>
-__global__ void __launch_bounds__(256) adaptive_kernel(BatchDev b, StoreDev st, int grow_margin, int shrink_margin)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) adaptive_kernel(BatchDev b, StoreDev st, int grow_margin, int shrink_margin)
 {
     __shared__ int lds_all[4][2 * WMAX];
     int *lds = lds_all[threadIdx.x >> 6];
