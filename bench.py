@@ -336,9 +336,12 @@ def seeds_main(args):
     dev_ms = float(np.median(ms))
     log(f"seeds: {s0['kmers']} k-mers, {s0['distinct']} distinct, {s0['reliable']} reliable, "
         f"{len(recs)} pairs in {dev_ms:.2f} ms")
-    # seed-and-extend of the pairs found, persistent form, records in HBM
+    # seed-and-extend of the pairs found, persistent form: the seed records
+    # are written to HBM and handed to the batch there
     n = len(recs)
-    d_recs = torch.from_numpy(recs.view(np.uint8).copy()).cuda()
+    d_recs = torch.zeros(n * 32, dtype=torch.uint8, device="cuda")
+    n_dev, _ = ctx.find_seeds_device(d_recs, n, k=31, lo=20, hi=30, x=15)
+    assert n_dev == n
     d_out = torch.zeros(n * 32, dtype=torch.uint8, device="cuda")
     d_cells = torch.zeros(n, dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()

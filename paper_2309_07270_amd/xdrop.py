@@ -220,6 +220,21 @@ class Context:
             return out[:found.value], st.as_dict()
         self._check(rc)
 
+    def find_seeds_device(self, d_out, max_records: int, k: int = 31, stride: int = 1, lo: int = 20, hi: int = 30,
+                          x: int = 15, weights=(1, -1, -1)):
+        """Seed records written straight into device memory (d_out: a torch
+        tensor or a device pointer with room for max_records 32-byte records);
+        returns (records found, statistics).  Records beyond max_records are
+        not written and the call raises XDROP_E_NOMEM."""
+        ma, mi, g = weights
+        prm = SeedParams(k, stride, lo, hi, x, ma, mi, g, 0)
+        ptr = d_out.data_ptr() if hasattr(d_out, "data_ptr") else d_out
+        found = ctypes.c_size_t()
+        st = SeedStats()
+        self._check(self.lib.xdrop_find_seeds(self.h, ctypes.byref(prm), ptr, max_records, 1,
+                                              ctypes.byref(found), ctypes.byref(st)))
+        return found.value, st.as_dict()
+
     def error(self) -> str:
         return self.lib.xdrop_last_error(self.h).decode()
 

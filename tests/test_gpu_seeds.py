@@ -115,3 +115,17 @@ def test_edge_cases(xd):
     with xd.Context(short) as ctx:
         recs, stats = ctx.find_seeds(k=11, lo=1, hi=5)
         assert len(recs) == 0 and stats["kmers"] == 0
+
+
+def test_device_output_equals_host_output(xd):
+    import torch
+    st = W.make_readset("c0", error=0.01, genome=15_000, coverage=20, seed=91)
+    note("device output of xdrop_find_seeds")
+    with xd.Context(st) as ctx:
+        host, _ = ctx.find_seeds(k=21, lo=3, hi=30)
+        d_out = torch.zeros(len(host) * 32, dtype=torch.uint8, device="cuda")
+        n, stats = ctx.find_seeds_device(d_out, len(host), k=21, lo=3, hi=30)
+        torch.cuda.synchronize()
+    dev = d_out.cpu().numpy().view(W.RECORD_DTYPE)
+    assert n == len(host) == stats["pairs"]
+    assert tuples(dev) == tuples(host)
