@@ -15,7 +15,7 @@ result write-back.  GCUPS counts the candidate cells of every extension
 (the oracle's definition; the GPU counting pass is verified against the
 oracle on the cpu_baseline sample).
 
-Prints one JSON line.  --gpus N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 exits: the benchmark measures one GPU.
 """
 from __future__ import annotations
 
@@ -109,8 +109,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
-              "(--gpus must be 1)", file=sys.stderr)
+        print("bench.py measures one GPU (--gpus must be 1); records are independent, so the path "
+              "shards by records across GPUs with one context per GPU", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

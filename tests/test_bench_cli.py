@@ -1,5 +1,5 @@
-"""bench.py command line on the CPU: this build measures one GPU, and asking
-for more exits with a message before anything touches a device."""
+"""bench.py command line on the CPU: the benchmark measures one GPU, and
+asking for more exits with a message before anything touches a device."""
 import os
 import subprocess
 import sys
