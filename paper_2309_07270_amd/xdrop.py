@@ -29,7 +29,7 @@ MAX_X = 1 << 30
 
 EXPORTED = ("xdrop_batch_create", "xdrop_batch_submit", "xdrop_batch_submit_device", "xdrop_batch_wait",
             "xdrop_batch_destroy", "xdrop_batch_footprint", "xdrop_get_tuning", "xdrop_set_tuning",
-            "xdrop_autotune", "xdrop_status_string", "xdrop_last_error")
+            "xdrop_autotune", "xdrop_find_seeds", "xdrop_status_string", "xdrop_last_error")
 
 
 class Config(ctypes.Structure):
