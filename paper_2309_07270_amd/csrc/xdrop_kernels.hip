@@ -963,18 +963,35 @@ __global__ void __launch_bounds__(256) wide_kernel(BatchDev b, StoreDev st, int 
 
 // ---------------------------------------------------------------------------
 // Unbounded X-drop extension: three anti-diagonals in global memory, indexed
-// by i, with the live range [lo, hi] of each; one wavefront sweeps the
-// candidate range of each anti-diagonal 64 cells at a time.
+// by i, with the live range [lo, hi] of each.  One workgroup of 1024 threads
+// runs one extension: its threads sweep the candidate range of an
+// anti-diagonal together, and one block reduction per anti-diagonal gives
+// the live range, the best value (smallest i on ties) and the cell count.
+// Used only for bands wider than the widest register window.
 // ---------------------------------------------------------------------------
+constexpr int kGenericThreads = 1024;
+
+// max of (value, -i) as one key: the high word holds value - NEG (> 0 for
+// every live value), the low word 0x7fffffff - i; 0 = no live cell
+__device__ __forceinline__ unsigned long long best_key(int v, int i)
+{
+    return ((unsigned long long)(uint32_t)(v - NEG) << 32) | (uint32_t)(0x7fffffff - i);
+}
+
 template <bool COUNT>
 __device__ void generic_run(const uint32_t *__restrict__ W, const Geo &g, int X, int ma, int mi, int gap,
-                            int *P2, int *P1, int *P0, int dummy, TaskOut &o)
+                            int *P2, int *P1, int *P0, TaskOut &o)
 {
-    const int lane = lane_id();
+    __shared__ int s_lo[kGenericThreads / 64], s_hi[kGenericThreads / 64];
+    __shared__ unsigned long long s_best[kGenericThreads / 64];
+    __shared__ uint32_t s_cells[kGenericThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    constexpr int NW = kGenericThreads / 64;
     const int m = g.m, n = g.n;
     int lo2 = 1, hi2 = 0, lo1 = 0, hi1 = 0;
-    P1[0] = 0;   // every lane writes the same value
+    if (tid == 0) P1[0] = 0;
     __threadfence_block();
+    __syncthreads();
     int T = 0, bi = 0, bj = 0;
     uint64_t cells = 0, slots = 0;
     bool prev_dead = false;
@@ -985,49 +1002,74 @@ __device__ void generic_run(const uint32_t *__restrict__ W, const Geo &g, int X,
         if (lo2 <= hi2) { slo = min(slo, lo2 + 1); shi = max(shi, hi2 + 1); }
         slo = max(slo, ilo);
         shi = min(shi, ihi);
-        int nlo = 1 << 30, nhi = -1, dmax = NEG, dmi = -1;
         const int thr = T - X;
-        for (int i0 = slo; i0 <= shi; i0 += 64) {
-            const int i = i0 + lane;
-            const bool act = i <= shi;
+        int nlo = 1 << 30, nhi = -1;
+        unsigned long long best = 0ull;
+        uint32_t cand_n = 0;
+        for (int i = slo + tid; i <= shi; i += kGenericThreads) {
             const int j = d - i;
-            // branch-free: every lane loads from clamped (always valid) indices
-            const int im1 = min(max(i - 1, 0), dummy), ic = min(max(i, 0), dummy);
-            const bool hd = act && i >= 1 && j >= 1 && i - 1 >= lo2 && i - 1 <= hi2;
-            const bool hu = act && i >= 1 && i - 1 >= lo1 && i - 1 <= hi1;
-            const bool hl = act && j >= 1 && i >= lo1 && i <= hi1;
-            const int pd = P2[im1], pu = P1[im1], pl = P1[ic];
-            const int ia = min(max(i - 1, 0), max(m - 1, 0)), jb = min(max(j - 1, 0), max(n - 1, 0));
-            const uint32_t ca = code_at(W, g.abase + (uint64_t)ia);
-            const uint32_t cb = code_at(W, g.bbase + (uint64_t)jb);
+            const bool hd = i >= 1 && j >= 1 && i - 1 >= lo2 && i - 1 <= hi2;
+            const bool hu = i >= 1 && i - 1 >= lo1 && i - 1 <= hi1;
+            const bool hl = j >= 1 && i >= lo1 && i <= hi1;
+            const int pd = hd ? P2[i - 1] : NEG, pu = hu ? P1[i - 1] : NEG, pl = hl ? P1[i] : NEG;
             const bool okd = hd && pd > NEG_HALF, oku = hu && pu > NEG_HALF, okl = hl && pl > NEG_HALF;
             int v = NEG;
-            v = max(v, okd ? pd + (ca == cb ? ma : mi) : NEG);
-            v = max(v, oku ? pu + gap : NEG);
-            v = max(v, okl ? pl + gap : NEG);
+            if (okd) {
+                const uint32_t ca = code_at(W, g.abase + (uint64_t)(i - 1));
+                const uint32_t cb = code_at(W, g.bbase + (uint64_t)(j - 1));
+                v = pd + (ca == cb ? ma : mi);
+            }
+            if (oku) v = max(v, pu + gap);
+            if (okl) v = max(v, pl + gap);
             const bool cand = okd || oku || okl;
             const bool lv = cand && v >= thr;
-            // lanes past the range write an index that is never read (no divergent branch)
-            P0[act ? i : dummy] = lv ? v : NEG;
-            if (COUNT) {
-                cells += (uint64_t)__builtin_popcountll(ballot(cand));
-                slots += 64u;
-            }
-            const uint64_t lmask = ballot(lv);
-            if (lmask) {
-                if (nhi < 0) nlo = i0 + __builtin_ctzll(lmask);
-                nhi = i0 + 63 - __builtin_clzll(lmask);
-                const int cmax = uni(wave_max(lv ? v : NEG));
-                if (cmax > dmax) {
-                    const uint64_t e = ballot(lv && v == cmax);
-                    dmax = cmax;
-                    dmi = i0 + __builtin_ctzll(e);
-                }
+            P0[i] = lv ? v : NEG;
+            cand_n += cand ? 1u : 0u;
+            if (lv) {
+                nlo = min(nlo, i);
+                nhi = max(nhi, i);
+                const unsigned long long key = best_key(v, i);
+                best = key > best ? key : best;
             }
         }
-        __threadfence_block();
+        // block reduction: wavefront by shuffles, then across wavefronts in LDS
+        for (int off = 32; off >= 1; off >>= 1) {
+            nlo = min(nlo, __shfl_xor(nlo, off, 64));
+            nhi = max(nhi, __shfl_xor(nhi, off, 64));
+            const unsigned long long ob = __shfl_xor(best, off, 64);
+            best = ob > best ? ob : best;
+            if (COUNT) cand_n += __shfl_xor(cand_n, off, 64);
+        }
+        if (lane == 0) {
+            s_lo[wid] = nlo;
+            s_hi[wid] = nhi;
+            s_best[wid] = best;
+            s_cells[wid] = cand_n;
+        }
+        __threadfence_block();   // P0 stores and the partials visible to the block
+        __syncthreads();
+        nlo = 1 << 30;
+        nhi = -1;
+        best = 0ull;
+        uint32_t cand_tot = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            nlo = min(nlo, s_lo[w]);
+            nhi = max(nhi, s_hi[w]);
+            best = s_best[w] > best ? s_best[w] : best;
+            cand_tot += s_cells[w];
+        }
+        __syncthreads();         // partials read before the next anti-diagonal writes them
+        if (COUNT) {
+            cells += cand_tot;
+            if (shi >= slo) slots += (uint64_t)((shi - slo + 64) / 64) * 64;
+        }
         const bool live = nhi >= 0;
-        if (live && dmax > T) { T = dmax; bi = dmi; bj = d - dmi; }
+        if (live) {
+            const int vmax = (int)(uint32_t)(best >> 32) + NEG;
+            const int imin = 0x7fffffff - (int)(uint32_t)(best & 0xffffffffull);
+            if (vmax > T) { T = vmax; bi = imin; bj = d - imin; }
+        }
         int *tp = P2; P2 = P1; P1 = P0; P0 = tp;
         lo2 = lo1; hi2 = hi1;
         lo1 = live ? nlo : 1; hi1 = live ? nhi : 0;
@@ -1038,22 +1080,26 @@ __device__ void generic_run(const uint32_t *__restrict__ W, const Geo &g, int X,
 }
 
 template <bool COUNT>
-__global__ void __launch_bounds__(256) generic_kernel(BatchDev b, StoreDev st, int32_t *scratch, uint64_t stride)
+__global__ void __launch_bounds__(kGenericThreads) generic_kernel(BatchDev b, StoreDev st, int32_t *scratch,
+                                                                  uint64_t stride)
 {
+    __shared__ uint32_t s_task;
     const uint32_t qcap = 2u * b.cap;
     const int cls = kGenericClass;
     const uint32_t cnt = b.ctr[CtrLayout::kCount + cls];
-    const uint64_t wave_global = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    int *base = scratch + wave_global * 3 * stride;
+    int *base = scratch + (uint64_t)blockIdx.x * 3 * stride;
     for (;;) {
-        const uint32_t idx = wave_fetch_add(&b.ctr[CtrLayout::kHead + cls], 1u);
-        if (idx >= cnt) break;
-        const uint32_t t = (uint32_t)uni((int)b.qbuf[cls * qcap + idx]);
+        if (threadIdx.x == 0) s_task = atomicAdd(&b.ctr[CtrLayout::kHead + cls], 1u);
+        __syncthreads();
+        const uint32_t idx = s_task;
+        __syncthreads();         // read by every thread before thread 0 writes it again
+        if (idx >= cnt) break;   // uniform over the block
+        const uint32_t t = b.qbuf[cls * qcap + idx];
         const Task k = load_task(b.recs, st.reads, t);
         TaskOut o;
-        generic_run<COUNT>(st.words, k.g, k.x, k.ma, k.mi, k.gap, base, base + stride, base + 2 * stride,
-                           (int)stride - 1, o);
-        b.tout[t] = o;   // same values in every lane
+        generic_run<COUNT>(st.words, k.g, k.x, k.ma, k.mi, k.gap, base, base + stride, base + 2 * stride, o);
+        if (threadIdx.x == 0) b.tout[t] = o;
+        __syncthreads();         // scratch of this task no longer read before the next one starts
     }
 }
 
@@ -1168,11 +1214,13 @@ void launch_wide(int which, const BatchDev &b, const StoreDev &st, uint32_t grid
 void launch_generic(const BatchDev &b, const StoreDev &st, int32_t *scratch, uint64_t stride, uint32_t grid_waves,
                     bool count_cells, hipStream_t s)
 {
-    const uint32_t blocks = grid_waves / 4;   // scratch holds exactly grid_waves (a multiple of 4) wavefronts
+    // one task per workgroup of kGenericThreads; the scratch holds three
+    // anti-diagonals for each of grid_waves wavefronts, more than the blocks use
+    const uint32_t blocks = max(1u, grid_waves / (kGenericThreads / 64));
     if (count_cells)
-        hipLaunchKernelGGL(generic_kernel<true>, dim3(blocks), dim3(256), 0, s, b, st, scratch, stride);
+        hipLaunchKernelGGL(generic_kernel<true>, dim3(blocks), dim3(kGenericThreads), 0, s, b, st, scratch, stride);
     else
-        hipLaunchKernelGGL(generic_kernel<false>, dim3(blocks), dim3(256), 0, s, b, st, scratch, stride);
+        hipLaunchKernelGGL(generic_kernel<false>, dim3(blocks), dim3(kGenericThreads), 0, s, b, st, scratch, stride);
 }
 
 void launch_finalize(const BatchDev &b, const StoreDev &st, uint32_t n, bool stage_sums, hipStream_t s)
