@@ -962,127 +962,205 @@ __global__ void __launch_bounds__(256) wide_kernel(BatchDev b, StoreDev st, int 
 }
 
 // ---------------------------------------------------------------------------
-// Unbounded X-drop extension: three anti-diagonals in global memory, indexed
-// by i, with the live range [lo, hi] of each.  One workgroup of 1024 threads
-// runs one extension: its threads sweep the candidate range of an
-// anti-diagonal together, and one block reduction per anti-diagonal gives
-// the live range, the best value (smallest i on ties) and the cell count.
-// Used only for bands wider than the widest register window.
+// Unbounded X-drop extension.  One workgroup of 1024 threads runs one
+// extension: its threads sweep the candidate range of an anti-diagonal
+// together, and one block reduction per anti-diagonal gives the live range,
+// the best value (smallest i on ties) and the cell count.  The last three
+// anti-diagonals sit in an LDS ring indexed by i mod kRing while every
+// candidate range fits it, then in global memory indexed by i.  Used only
+// for bands wider than the widest register window.
 // ---------------------------------------------------------------------------
 constexpr int kGenericThreads = 1024;
+constexpr int kGenericWaves = kGenericThreads / 64;
+constexpr int kRing = 8192;   // LDS ring slots per anti-diagonal (power of two)
 
-// max of (value, -i) as one key: the high word holds value - NEG (> 0 for
-// every live value), the low word 0x7fffffff - i; 0 = no live cell
-__device__ __forceinline__ unsigned long long best_key(int v, int i)
+struct GState {
+    int d;                 // next anti-diagonal
+    int lo1, hi1;          // live range of d-1 (lo > hi: none)
+    int lo2, hi2;          // live range of d-2
+    int T, bi, bj;         // best so far and its cell
+    uint64_t cells, slots;
+    bool prev_dead;        // d-1 had no live cell
+};
+
+// per-wavefront partial of one anti-diagonal
+struct GPart {
+    int lo, hi, v, i;
+    uint32_t cells, pad[3];
+};
+
+// Whole-wavefront reduction with DPP (quad permutes, row mirrors, then the
+// row broadcasts of lanes 15 and 31); the result is read from lane 63.
+template <typename Op>
+__device__ __forceinline__ int wave_reduce(int v, int ident, Op op)
 {
-    return ((unsigned long long)(uint32_t)(v - NEG) << 32) | (uint32_t)(0x7fffffff - i);
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0xB1, 0xf, 0xf, false));    // quad_perm [1,0,3,2]
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x4E, 0xf, 0xf, false));    // quad_perm [2,3,0,1]
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x141, 0xf, 0xf, false));   // row_half_mirror
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x140, 0xf, 0xf, false));   // row_mirror
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x142, 0xa, 0xf, false));   // row_bcast:15 -> rows 1, 3
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x143, 0xc, 0xf, false));   // row_bcast:31 -> rows 2, 3
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// The same over each row of 16 lanes (every lane of a row ends with its row's
+// result), read from lane 0.
+template <typename Op>
+__device__ __forceinline__ int row_reduce(int v, int ident, Op op)
+{
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0xB1, 0xf, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x4E, 0xf, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x141, 0xf, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x140, 0xf, 0xf, false));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+struct OpMin { __device__ int operator()(int a, int b) const { return min(a, b); } };
+struct OpMax { __device__ int operator()(int a, int b) const { return max(a, b); } };
+struct OpAdd { __device__ int operator()(int a, int b) const { return a + b; } };
+
+// Anti-diagonals s.d, s.d+1, ... with the previous two in P1 and P2 (RING:
+// LDS slots i mod kRing; else global arrays indexed by i).  Returns true when
+// the extension has ended; false (RING only) before an anti-diagonal whose
+// candidate range does not fit the ring, with the state of the last one done
+// and P1 / P2 pointing at the arrays of s.d-1 / s.d-2.
+template <bool COUNT, bool RING>
+__device__ bool generic_diags(const uint32_t *__restrict__ W, const Geo &g, int X, int ma, int mi, int gap,
+                              int *&P2, int *&P1, int *&P0, GState &s, GPart (*part)[kGenericWaves])
+{
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    constexpr uint32_t MASK = RING ? (uint32_t)kRing - 1u : 0xffffffffu;
+    const int m = g.m, n = g.n;
+    const uint32_t *aseq = W + (g.abase >> 4), *bseq = W + (g.bbase >> 4);
+    const int aph = (int)(g.abase & 15) - 1, bph = (int)(g.bbase & 15) - 1;   // a_i = code aph + i
+    for (; s.d <= m + n; ++s.d) {
+        const int d = s.d;
+        // candidates: successors of live cells on d-1 (i, i+1) and on d-2 (i+1), inside the table
+        int slo = 1 << 30, shi = -(1 << 30);
+        if (s.lo1 <= s.hi1) { slo = min(slo, s.lo1); shi = max(shi, s.hi1 + 1); }
+        if (s.lo2 <= s.hi2) { slo = min(slo, s.lo2 + 1); shi = max(shi, s.hi2 + 1); }
+        slo = max(slo, max(0, d - n));
+        shi = min(shi, min(m, d));
+        if (RING && shi - slo + 1 > kRing) return false;   // uniform over the block
+        const int thr = s.T - X;
+        int nlo = 1 << 30, nhi = -1, bv = NEG, bidx = 1 << 30, cand_n = 0;
+        for (int i = slo + tid; i <= shi; i += kGenericThreads) {
+            // a live range lies inside the table of its anti-diagonal, so a
+            // predecessor inside it has i >= 0 and j >= 0
+            const bool hd = i - 1 >= s.lo2 && i - 1 <= s.hi2;
+            const bool hu = i - 1 >= s.lo1 && i - 1 <= s.hi1;
+            const bool hl = i >= s.lo1 && i <= s.hi1;
+            // codes of a_i and b_j (i, j >= 0: at worst one base before the
+            // sequence, inside the store's guard words), loaded before the
+            // predecessors so that both latencies overlap
+            const int pa = aph + i, pb = bph + (d - i);
+            const uint32_t wa = aseq[pa >> 4], wb = bseq[pb >> 4];
+            int pd, pu, pl;
+            if (RING) {
+                // every ring slot is inside the array: load, then select
+                pd = P2[(uint32_t)(i - 1) & MASK];
+                pu = P1[(uint32_t)(i - 1) & MASK];
+                pl = P1[(uint32_t)i & MASK];
+                pd = hd ? pd : NEG;
+                pu = hu ? pu : NEG;
+                pl = hl ? pl : NEG;
+            } else {
+                pd = hd ? P2[i - 1] : NEG;
+                pu = hu ? P1[i - 1] : NEG;
+                pl = hl ? P1[i] : NEG;
+            }
+            // keeps the code loads above this point (the compiler would sink
+            // them into the diagonal-move branch, after the predecessor loads)
+            asm volatile("" ::"v"(wa), "v"(wb));
+            const bool okd = pd > NEG_HALF, oku = pu > NEG_HALF, okl = pl > NEG_HALF;
+            const uint32_t ca = __builtin_amdgcn_ubfe(wa, (uint32_t)(pa & 15) * 2u, 2u);
+            const uint32_t cb = __builtin_amdgcn_ubfe(wb, (uint32_t)(pb & 15) * 2u, 2u);
+            int v = okd ? pd + (ca == cb ? ma : mi) : NEG;
+            v = oku ? max(v, pu + gap) : v;
+            v = okl ? max(v, pl + gap) : v;
+            const bool cand = okd || oku || okl;
+            const bool lv = cand && v >= thr;
+            P0[(uint32_t)i & MASK] = lv ? v : NEG;
+            if (COUNT) cand_n += cand ? 1 : 0;
+            nlo = lv ? min(nlo, i) : nlo;
+            nhi = lv ? max(nhi, i) : nhi;
+            const bool up = lv && v > bv;   // i rises along the loop: first i kept on ties
+            bidx = up ? i : bidx;
+            bv = up ? v : bv;
+        }
+        // wavefront partials, then every thread reduces the partials of all wavefronts
+        GPart *pp = part[d & 1];
+        {
+            const int wlo = wave_reduce(nlo, 1 << 30, OpMin());
+            const int whi = wave_reduce(nhi, -1, OpMax());
+            const int wv = wave_reduce(bv, NEG, OpMax());
+            const int wi = wave_reduce(bv == wv ? bidx : 1 << 30, 1 << 30, OpMin());
+            const int wc = COUNT ? wave_reduce(cand_n, 0, OpAdd()) : 0;
+            if (lane == 0) {
+                GPart q;
+                q.lo = wlo; q.hi = whi; q.v = wv; q.i = wi; q.cells = (uint32_t)wc;
+                q.pad[0] = q.pad[1] = q.pad[2] = 0;
+                pp[wid] = q;
+            }
+        }
+        // One barrier per anti-diagonal: it orders this anti-diagonal's
+        // stores before the next one's loads.  The partials alternate
+        // between two buffers and the three anti-diagonal arrays rotate, so a
+        // location is written again only after every thread has passed the
+        // barrier that follows its last read.
+        __syncthreads();
+        // lane l of every row of 16 reads the partial of wavefront l
+        static_assert(kGenericWaves == 16, "one partial per lane of a DPP row");
+        const GPart q = pp[lane & 15];
+        nlo = row_reduce(q.lo, 1 << 30, OpMin());
+        nhi = row_reduce(q.hi, -1, OpMax());
+        const int vmax = row_reduce(q.v, NEG, OpMax());
+        const int imin = row_reduce(q.v == vmax ? q.i : 1 << 30, 1 << 30, OpMin());
+        const uint32_t ctot = COUNT ? (uint32_t)row_reduce((int)q.cells, 0, OpAdd()) : 0u;
+        if (COUNT) {
+            s.cells += ctot;
+            if (shi >= slo) s.slots += (uint64_t)((shi - slo + 64) / 64) * 64;
+        }
+        const bool live = nhi >= 0;
+        if (live && vmax > s.T) { s.T = vmax; s.bi = imin; s.bj = d - imin; }
+        int *tp = P2; P2 = P1; P1 = P0; P0 = tp;
+        s.lo2 = s.lo1; s.hi2 = s.hi1;
+        s.lo1 = live ? nlo : 1; s.hi1 = live ? nhi : 0;
+        if (!live && s.prev_dead) return true;
+        s.prev_dead = !live;
+    }
+    return true;
 }
 
 template <bool COUNT>
 __device__ void generic_run(const uint32_t *__restrict__ W, const Geo &g, int X, int ma, int mi, int gap,
-                            int *P2, int *P1, int *P0, TaskOut &o)
+                            int *ring, int *G2, int *G1, int *G0, GPart (*part)[kGenericWaves], TaskOut &o)
 {
-    __shared__ int s_lo[kGenericThreads / 64], s_hi[kGenericThreads / 64];
-    __shared__ unsigned long long s_best[kGenericThreads / 64];
-    __shared__ uint32_t s_cells[kGenericThreads / 64];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    constexpr int NW = kGenericThreads / 64;
-    const int m = g.m, n = g.n;
-    int lo2 = 1, hi2 = 0, lo1 = 0, hi1 = 0;
-    if (tid == 0) P1[0] = 0;
-    __threadfence_block();
+    const int tid = threadIdx.x;
+    GState s;
+    s.d = 1; s.lo1 = 0; s.hi1 = 0; s.lo2 = 1; s.hi2 = 0;
+    s.T = 0; s.bi = 0; s.bj = 0; s.cells = 0; s.slots = 0; s.prev_dead = false;
+    int *P0 = ring, *P1 = ring + kRing, *P2 = ring + 2 * kRing;
+    if (tid == 0) P1[0] = 0;   // anti-diagonal 0: S(0,0) = 0
     __syncthreads();
-    int T = 0, bi = 0, bj = 0;
-    uint64_t cells = 0, slots = 0;
-    bool prev_dead = false;
-    for (int d = 1; d <= m + n; ++d) {
-        const int ilo = max(0, d - n), ihi = min(m, d);
-        int slo = 1 << 30, shi = -(1 << 30);
-        if (lo1 <= hi1) { slo = min(slo, lo1); shi = max(shi, hi1 + 1); }
-        if (lo2 <= hi2) { slo = min(slo, lo2 + 1); shi = max(shi, hi2 + 1); }
-        slo = max(slo, ilo);
-        shi = min(shi, ihi);
-        const int thr = T - X;
-        int nlo = 1 << 30, nhi = -1;
-        unsigned long long best = 0ull;
-        uint32_t cand_n = 0;
-        for (int i = slo + tid; i <= shi; i += kGenericThreads) {
-            const int j = d - i;
-            const bool hd = i >= 1 && j >= 1 && i - 1 >= lo2 && i - 1 <= hi2;
-            const bool hu = i >= 1 && i - 1 >= lo1 && i - 1 <= hi1;
-            const bool hl = j >= 1 && i >= lo1 && i <= hi1;
-            const int pd = hd ? P2[i - 1] : NEG, pu = hu ? P1[i - 1] : NEG, pl = hl ? P1[i] : NEG;
-            const bool okd = hd && pd > NEG_HALF, oku = hu && pu > NEG_HALF, okl = hl && pl > NEG_HALF;
-            int v = NEG;
-            if (okd) {
-                const uint32_t ca = code_at(W, g.abase + (uint64_t)(i - 1));
-                const uint32_t cb = code_at(W, g.bbase + (uint64_t)(j - 1));
-                v = pd + (ca == cb ? ma : mi);
-            }
-            if (oku) v = max(v, pu + gap);
-            if (okl) v = max(v, pl + gap);
-            const bool cand = okd || oku || okl;
-            const bool lv = cand && v >= thr;
-            P0[i] = lv ? v : NEG;
-            cand_n += cand ? 1u : 0u;
-            if (lv) {
-                nlo = min(nlo, i);
-                nhi = max(nhi, i);
-                const unsigned long long key = best_key(v, i);
-                best = key > best ? key : best;
-            }
-        }
-        // block reduction: wavefront by shuffles, then across wavefronts in LDS
-        for (int off = 32; off >= 1; off >>= 1) {
-            nlo = min(nlo, __shfl_xor(nlo, off, 64));
-            nhi = max(nhi, __shfl_xor(nhi, off, 64));
-            const unsigned long long ob = __shfl_xor(best, off, 64);
-            best = ob > best ? ob : best;
-            if (COUNT) cand_n += __shfl_xor(cand_n, off, 64);
-        }
-        if (lane == 0) {
-            s_lo[wid] = nlo;
-            s_hi[wid] = nhi;
-            s_best[wid] = best;
-            s_cells[wid] = cand_n;
-        }
-        __threadfence_block();   // P0 stores and the partials visible to the block
+    if (!generic_diags<COUNT, true>(W, g, X, ma, mi, gap, P2, P1, P0, s, part)) {
+        // the band outgrew the ring: the live cells of the last two
+        // anti-diagonals move to global memory
+        for (int i = s.lo1 + tid; i <= s.hi1; i += kGenericThreads) G1[i] = P1[(uint32_t)i & (kRing - 1)];
+        for (int i = s.lo2 + tid; i <= s.hi2; i += kGenericThreads) G2[i] = P2[(uint32_t)i & (kRing - 1)];
+        __threadfence_block();
         __syncthreads();
-        nlo = 1 << 30;
-        nhi = -1;
-        best = 0ull;
-        uint32_t cand_tot = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            nlo = min(nlo, s_lo[w]);
-            nhi = max(nhi, s_hi[w]);
-            best = s_best[w] > best ? s_best[w] : best;
-            cand_tot += s_cells[w];
-        }
-        __syncthreads();         // partials read before the next anti-diagonal writes them
-        if (COUNT) {
-            cells += cand_tot;
-            if (shi >= slo) slots += (uint64_t)((shi - slo + 64) / 64) * 64;
-        }
-        const bool live = nhi >= 0;
-        if (live) {
-            const int vmax = (int)(uint32_t)(best >> 32) + NEG;
-            const int imin = 0x7fffffff - (int)(uint32_t)(best & 0xffffffffull);
-            if (vmax > T) { T = vmax; bi = imin; bj = d - imin; }
-        }
-        int *tp = P2; P2 = P1; P1 = P0; P0 = tp;
-        lo2 = lo1; hi2 = hi1;
-        lo1 = live ? nlo : 1; hi1 = live ? nhi : 0;
-        if (!live && prev_dead) break;
-        prev_dead = !live;
+        generic_diags<COUNT, false>(W, g, X, ma, mi, gap, G2, G1, G0, s, part);
     }
-    o.score = T; o.i = bi; o.j = bj; o.status = (uint32_t)kGenericClass; o.cells = cells; o.slots = slots;
+    o.score = s.T; o.i = s.bi; o.j = s.bj; o.status = (uint32_t)kGenericClass; o.cells = s.cells; o.slots = s.slots;
 }
 
 template <bool COUNT>
 __global__ void __launch_bounds__(kGenericThreads) generic_kernel(BatchDev b, StoreDev st, int32_t *scratch,
                                                                   uint64_t stride)
 {
+    __shared__ int ring[3 * kRing];
+    __shared__ GPart part[2][kGenericWaves];
     __shared__ uint32_t s_task;
     const uint32_t qcap = 2u * b.cap;
     const int cls = kGenericClass;
@@ -1097,9 +1175,10 @@ __global__ void __launch_bounds__(kGenericThreads) generic_kernel(BatchDev b, St
         const uint32_t t = b.qbuf[cls * qcap + idx];
         const Task k = load_task(b.recs, st.reads, t);
         TaskOut o;
-        generic_run<COUNT>(st.words, k.g, k.x, k.ma, k.mi, k.gap, base, base + stride, base + 2 * stride, o);
+        generic_run<COUNT>(st.words, k.g, k.x, k.ma, k.mi, k.gap, ring, base, base + stride, base + 2 * stride,
+                           part, o);
         if (threadIdx.x == 0) b.tout[t] = o;
-        __syncthreads();         // scratch of this task no longer read before the next one starts
+        __syncthreads();         // ring and scratch of this task no longer read before the next one starts
     }
 }
 

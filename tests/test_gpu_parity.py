@@ -102,6 +102,34 @@ def test_wide_bands_escalate(xd):
     assert_same(res, cells, ref)
 
 
+def test_unbounded_band_wider_than_lds_ring(xd):
+    # X = 2^30 on 9-9.6 kb reads: the candidate range of the middle
+    # anti-diagonals is about 9,000 cells, wider than the unbounded kernel's
+    # 8,192-slot LDS ring, so the extension moves to global memory part way;
+    # X = 4000 on the same reads stays in the ring
+    rng = np.random.Generator(np.random.PCG64(33))
+    a = rng.integers(0, 4, 9600).astype(np.uint8)
+    b = a[200:9400].copy()
+    flip = rng.random(b.size) < 0.1
+    b[flip] = (b[flip] + rng.integers(1, 4, int(flip.sum()))) % 4
+    c = rng.integers(0, 4, 9300).astype(np.uint8)
+    store = W.ReadStore(np.concatenate([a, b, c]), np.array([0, 9600, 9600 + 9200]),
+                        np.array([9600, 9200, 9300]))
+    recs = np.zeros(4, W.RECORD_DTYPE)
+    recs["read_a"] = [0, 0, 0, 1]
+    recs["read_b"] = [1, 2, 2, 2]
+    recs["pos_a"] = [0, 9590, 0, 4000]
+    recs["pos_b"] = [0, 9290, 0, 4000]
+    recs["k"] = [3, 3, 3, 5]
+    recs["x"] = [1 << 30, 1 << 30, 4000, 4000]
+    recs["match"], recs["mismatch"], recs["gap"] = 1, -1, -1
+    ref, _ = oracle.batch(store.codes, store.off, store.length, recs)
+    note("unbounded band wider than the LDS ring: 9-9.6 kb reads, X = 2^30 and 4000")
+    with xd.Context(store) as ctx:
+        res, cells, _ = ctx.run(recs, count_cells=True)
+    assert_same(res, cells, ref)
+
+
 def test_identical_reads_full_length(xd):
     rng = np.random.Generator(np.random.PCG64(5))
     seq = rng.integers(0, 4, 3000).astype(np.uint8)
