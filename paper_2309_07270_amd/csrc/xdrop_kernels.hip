@@ -989,11 +989,28 @@ struct GPart {
     uint32_t cells, pad[3];
 };
 
+// the identity of each operation is passed as the DPP "old" value, so that
+// lanes without a source keep their value and mov_dpp + op fuse into one
+// DPP-modified instruction
+struct OpMin {
+    static constexpr int kIdent = 0x7fffffff;
+    __device__ int operator()(int a, int b) const { return min(a, b); }
+};
+struct OpMax {
+    static constexpr int kIdent = -0x7fffffff - 1;
+    __device__ int operator()(int a, int b) const { return max(a, b); }
+};
+struct OpAdd {
+    static constexpr int kIdent = 0;
+    __device__ int operator()(int a, int b) const { return a + b; }
+};
+
 // Whole-wavefront reduction with DPP (quad permutes, row mirrors, then the
 // row broadcasts of lanes 15 and 31); the result is read from lane 63.
 template <typename Op>
-__device__ __forceinline__ int wave_reduce(int v, int ident, Op op)
+__device__ __forceinline__ int wave_reduce(int v, Op op)
 {
+    constexpr int ident = Op::kIdent;
     v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0xB1, 0xf, 0xf, false));    // quad_perm [1,0,3,2]
     v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x4E, 0xf, 0xf, false));    // quad_perm [2,3,0,1]
     v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x141, 0xf, 0xf, false));   // row_half_mirror
@@ -1006,18 +1023,15 @@ __device__ __forceinline__ int wave_reduce(int v, int ident, Op op)
 // The same over each row of 16 lanes (every lane of a row ends with its row's
 // result), read from lane 0.
 template <typename Op>
-__device__ __forceinline__ int row_reduce(int v, int ident, Op op)
+__device__ __forceinline__ int row_reduce(int v, Op op)
 {
+    constexpr int ident = Op::kIdent;
     v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0xB1, 0xf, 0xf, false));
     v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x4E, 0xf, 0xf, false));
     v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x141, 0xf, 0xf, false));
     v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x140, 0xf, 0xf, false));
     return __builtin_amdgcn_readfirstlane(v);
 }
-
-struct OpMin { __device__ int operator()(int a, int b) const { return min(a, b); } };
-struct OpMax { __device__ int operator()(int a, int b) const { return max(a, b); } };
-struct OpAdd { __device__ int operator()(int a, int b) const { return a + b; } };
 
 // Anti-diagonals s.d, s.d+1, ... with the previous two in P1 and P2 (RING:
 // LDS slots i mod kRing; else global arrays indexed by i).  Returns true when
@@ -1043,7 +1057,11 @@ __device__ bool generic_diags(const uint32_t *__restrict__ W, const Geo &g, int 
         shi = min(shi, min(m, d));
         if (RING && shi - slo + 1 > kRing) return false;   // uniform over the block
         const int thr = s.T - X;
-        int nlo = 1 << 30, nhi = -1, bv = NEG, bidx = 1 << 30, cand_n = 0;
+        // wave-uniform live range and candidate count from ballots (the
+        // lanes of a wavefront hold consecutive i in every pass of the loop);
+        // per lane the best value and its first i
+        int wlo = 0x7fffffff, whi = -1, bv = NEG, bidx = 0x7fffffff;
+        uint32_t wcand = 0;
         for (int i = slo + tid; i <= shi; i += kGenericThreads) {
             // a live range lies inside the table of its anti-diagonal, so a
             // predecessor inside it has i >= 0 and j >= 0
@@ -1081,9 +1099,13 @@ __device__ bool generic_diags(const uint32_t *__restrict__ W, const Geo &g, int 
             const bool cand = okd || oku || okl;
             const bool lv = cand && v >= thr;
             P0[(uint32_t)i & MASK] = lv ? v : NEG;
-            if (COUNT) cand_n += cand ? 1 : 0;
-            nlo = lv ? min(nlo, i) : nlo;
-            nhi = lv ? max(nhi, i) : nhi;
+            if (COUNT) wcand += (uint32_t)__builtin_popcountll(ballot(cand));
+            const uint64_t lm = ballot(lv);
+            if (lm) {
+                const int i0 = uni(i - lane);   // i of lane 0 in this pass
+                wlo = min(wlo, i0 + (int)__builtin_ctzll(lm));
+                whi = max(whi, i0 + 63 - (int)__builtin_clzll(lm));
+            }
             const bool up = lv && v > bv;   // i rises along the loop: first i kept on ties
             bidx = up ? i : bidx;
             bv = up ? v : bv;
@@ -1091,14 +1113,16 @@ __device__ bool generic_diags(const uint32_t *__restrict__ W, const Geo &g, int 
         // wavefront partials, then every thread reduces the partials of all wavefronts
         GPart *pp = part[d & 1];
         {
-            const int wlo = wave_reduce(nlo, 1 << 30, OpMin());
-            const int whi = wave_reduce(nhi, -1, OpMax());
-            const int wv = wave_reduce(bv, NEG, OpMax());
-            const int wi = wave_reduce(bv == wv ? bidx : 1 << 30, 1 << 30, OpMin());
-            const int wc = COUNT ? wave_reduce(cand_n, 0, OpAdd()) : 0;
+            const int wv = wave_reduce(bv, OpMax());
+            // smallest i holding the maximum: the lowest such lane unless
+            // several passes of the loop hold it
+            const uint64_t at = ballot(bv == wv);
+            int wi = __builtin_amdgcn_readlane(bidx, (int)__builtin_ctzll(at | (1ull << 63)));
+            if (shi - slo >= kGenericThreads && __builtin_popcountll(at) > 1)
+                wi = wave_reduce(bv == wv ? bidx : 0x7fffffff, OpMin());
             if (lane == 0) {
                 GPart q;
-                q.lo = wlo; q.hi = whi; q.v = wv; q.i = wi; q.cells = (uint32_t)wc;
+                q.lo = wlo; q.hi = whi; q.v = wv; q.i = wi; q.cells = wcand;
                 q.pad[0] = q.pad[1] = q.pad[2] = 0;
                 pp[wid] = q;
             }
@@ -1112,11 +1136,11 @@ __device__ bool generic_diags(const uint32_t *__restrict__ W, const Geo &g, int 
         // lane l of every row of 16 reads the partial of wavefront l
         static_assert(kGenericWaves == 16, "one partial per lane of a DPP row");
         const GPart q = pp[lane & 15];
-        nlo = row_reduce(q.lo, 1 << 30, OpMin());
-        nhi = row_reduce(q.hi, -1, OpMax());
-        const int vmax = row_reduce(q.v, NEG, OpMax());
-        const int imin = row_reduce(q.v == vmax ? q.i : 1 << 30, 1 << 30, OpMin());
-        const uint32_t ctot = COUNT ? (uint32_t)row_reduce((int)q.cells, 0, OpAdd()) : 0u;
+        const int nlo = row_reduce(q.lo, OpMin());
+        const int nhi = row_reduce(q.hi, OpMax());
+        const int vmax = row_reduce(q.v, OpMax());
+        const int imin = row_reduce(q.v == vmax ? q.i : 0x7fffffff, OpMin());
+        const uint32_t ctot = COUNT ? (uint32_t)row_reduce((int)q.cells, OpAdd()) : 0u;
         if (COUNT) {
             s.cells += ctot;
             if (shi >= slo) s.slots += (uint64_t)((shi - slo + 64) / 64) * 64;
