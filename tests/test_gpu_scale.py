@@ -105,3 +105,13 @@ def test_c4_stress_mix_sampled(xd, name):
     res, cells, st = run_device(xd, wl, xd.MODE_PERSISTENT)
     check_properties(wl, res)
     check_sample(wl, res, cells, 40 if name == "c4" else 150, 3)
+
+
+def test_c4b_full_size(xd):
+    # the whole 2M-pair mix under +1/-2/-2: unrelated pairs die after a few
+    # hundred anti-diagonals, true overlaps extend to a read end
+    wl = W.make_workload("c4b")
+    note(f"c4b full size: {len(wl.records)} records")
+    res, cells, st = run_device(xd, wl, xd.MODE_PERSISTENT)
+    check_properties(wl, res)
+    check_sample(wl, res, cells, 200, 4)
