@@ -178,7 +178,8 @@ typedef struct {
                                      per lane with this many free slots per side (>= 2) */
     int32_t waves_per_cu;         /* persistent grid: wavefronts per compute unit           */
     int32_t buckets;              /* 1: order extensions longest-first; 0: arrival order   */
-    int32_t generic_waves;        /* grid of the unbounded-band kernel (multiple of 4)     */
+    int32_t generic_waves;        /* grid of the unbounded-band kernel, in wavefronts: one
+                                     workgroup of 16 per extension (multiple of 16)          */
 } xdrop_tuning;
 
 /* Current launch parameters of a context. */

@@ -102,7 +102,7 @@ struct Slot {
     void *dblock = nullptr;
     int32_t *scratch = nullptr;       // generic-kernel diagonals
     uint64_t scratch_stride = 0;
-    uint32_t generic_waves = 0;
+    uint32_t generic_blocks = 0;      // workgroups of the unbounded kernel
     BatchDev dev{};
     uint32_t *d_n = nullptr;          // batch size word read by the reset kernel
     xdrop_record *h_recs = nullptr;   // pinned staging
@@ -285,11 +285,11 @@ void alloc_slot_buffers(xdrop_ctx *c, Slot &s, uint32_t cap)
     s.dev.bucket_hist = (uint32_t *)take((size_t)kNumClasses * kNumBuckets * sizeof(uint32_t));
     s.dev.stage_sum = (unsigned long long *)take(kStageSumWords * sizeof(unsigned long long));
     s.dev.cap = cap;
-    // generic-kernel scratch: three anti-diagonals per wavefront
-    s.generic_waves = (uint32_t)((std::max(4, c->tune.generic_waves) + 3) / 4 * 4);   // whole blocks of 4
+    // unbounded-kernel scratch: three anti-diagonals per workgroup
+    s.generic_blocks = generic_blocks(c->tune.generic_waves);
     s.scratch_stride = ((uint64_t)c->st.max_len + 2 + 63) & ~uint64_t(63);
-    HIP_TRY(hipMalloc(&s.scratch, (size_t)s.generic_waves * 3 * s.scratch_stride * sizeof(int32_t)));
-    s.bytes += (size_t)s.generic_waves * 3 * s.scratch_stride * sizeof(int32_t);
+    HIP_TRY(hipMalloc(&s.scratch, (size_t)s.generic_blocks * 3 * s.scratch_stride * sizeof(int32_t)));
+    s.bytes += (size_t)s.generic_blocks * 3 * s.scratch_stride * sizeof(int32_t);
     HIP_TRY(hipHostMalloc((void **)&s.h_recs, n * sizeof(xdrop_record), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void **)&s.h_res, n * sizeof(xdrop_result), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void **)&s.h_cells, n * sizeof(uint64_t), hipHostMallocDefault));
@@ -306,7 +306,7 @@ void alloc_slot_buffers(xdrop_ctx *c, Slot &s, uint32_t cap)
 size_t slot_footprint(const xdrop_ctx *c, uint32_t cap)
 {
     const uint64_t stride = ((uint64_t)c->st.max_len + 2 + 63) & ~uint64_t(63);
-    return slot_bytes(cap) + (size_t)((std::max(4, c->tune.generic_waves) + 3) / 4 * 4) * 3 * stride * sizeof(int32_t);
+    return slot_bytes(cap) + (size_t)generic_blocks(c->tune.generic_waves) * 3 * stride * sizeof(int32_t);
 }
 
 uint32_t round_cap(size_t n)
@@ -336,7 +336,7 @@ void enqueue_kernels(xdrop_ctx *c, Slot &sl, const BatchDev &b, uint32_t n, cons
         launch_wide(w, b, c->st, (uint32_t)c->cus * 8u, count, s);
         if (ev) HIP_TRY(hipEventRecord(ev[3 + w], s));
     }
-    launch_generic(b, c->st, sl.scratch, sl.scratch_stride, sl.generic_waves, count, s);
+    launch_generic(b, c->st, sl.scratch, sl.scratch_stride, sl.generic_blocks, count, s);
     if (ev) HIP_TRY(hipEventRecord(ev[2 + kNumClasses - 1], s));
     launch_finalize(b, c->st, n, count, s);
     if (ev) HIP_TRY(hipEventRecord(ev[kNumStages], s));
@@ -605,14 +605,15 @@ void clamp_tuning(Tuning &t)
     t.shrink_margin = std::min(std::max(t.shrink_margin, 2), 64);
     t.waves_per_cu = std::min(std::max(t.waves_per_cu, 1), 64);
     t.buckets = t.buckets ? 1 : 0;
-    t.generic_waves = (std::min(std::max(t.generic_waves, 4), 4096) + 3) / 4 * 4;
+    t.generic_waves = (std::min(std::max(t.generic_waves, kGenericBlockWaves), 4096) + kGenericBlockWaves - 1) /
+                      kGenericBlockWaves * kGenericBlockWaves;
 }
 
 // new launch parameters: captured graphs hold the old ones; the unbounded
-// kernel's scratch is sized by generic_waves (called with c->mu held, idle)
+// kernel's scratch is sized by its workgroup count (called with c->mu held, idle)
 void apply_tuning(xdrop_ctx *c, const Tuning &t)
 {
-    const bool rescratch = t.generic_waves != c->tune.generic_waves;
+    const bool rescratch = generic_blocks(t.generic_waves) != generic_blocks(c->tune.generic_waves);
     c->tune = t;
     for (auto &sl : c->slots) {
         for (auto &g : sl->graph)

@@ -101,8 +101,16 @@ void launch_adaptive(const BatchDev &b, const StoreDev &st, const Tuning &tu, ui
                      bool count_cells, hipStream_t s);
 void launch_wide(int which, const BatchDev &b, const StoreDev &st, uint32_t grid_waves, bool count_cells,
                  hipStream_t s);
+// Unbounded kernel: one workgroup of kGenericBlockWaves wavefronts per
+// extension; `blocks` workgroups, each with three anti-diagonals of
+// scratch_stride ints in `scratch` (used only by bands wider than its LDS ring).
+constexpr int kGenericBlockWaves = 16;
+inline uint32_t generic_blocks(int32_t generic_waves)
+{
+    return generic_waves >= kGenericBlockWaves ? (uint32_t)generic_waves / kGenericBlockWaves : 1u;
+}
 void launch_generic(const BatchDev &b, const StoreDev &st, int32_t *scratch, uint64_t scratch_stride,
-                    uint32_t grid_waves, bool count_cells, hipStream_t s);
+                    uint32_t blocks, bool count_cells, hipStream_t s);
 void launch_finalize(const BatchDev &b, const StoreDev &st, uint32_t n, bool stage_sums, hipStream_t s);
 
 // Seed discovery: device tables of one call (see seed_kernels.hip).

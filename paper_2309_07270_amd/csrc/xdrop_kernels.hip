@@ -970,8 +970,8 @@ __global__ void __launch_bounds__(256) wide_kernel(BatchDev b, StoreDev st, int 
 // candidate range fits it, then in global memory indexed by i.  Used only
 // for bands wider than the widest register window.
 // ---------------------------------------------------------------------------
-constexpr int kGenericThreads = 1024;
-constexpr int kGenericWaves = kGenericThreads / 64;
+constexpr int kGenericWaves = kGenericBlockWaves;
+constexpr int kGenericThreads = 64 * kGenericWaves;
 constexpr int kRing = 8192;   // LDS ring slots per anti-diagonal (power of two)
 
 struct GState {
@@ -1314,12 +1314,12 @@ void launch_wide(int which, const BatchDev &b, const StoreDev &st, uint32_t grid
     else launch_wide_c<32>(b, st, 1 + which, grid_waves, count_cells, s);
 }
 
-void launch_generic(const BatchDev &b, const StoreDev &st, int32_t *scratch, uint64_t stride, uint32_t grid_waves,
+void launch_generic(const BatchDev &b, const StoreDev &st, int32_t *scratch, uint64_t stride, uint32_t blocks,
                     bool count_cells, hipStream_t s)
 {
-    // one task per workgroup of kGenericThreads; the scratch holds three
-    // anti-diagonals for each of grid_waves wavefronts, more than the blocks use
-    const uint32_t blocks = max(1u, grid_waves / (kGenericThreads / 64));
+    // one task per workgroup of kGenericThreads; workgroup k owns
+    // scratch[3 * stride * k, 3 * stride * (k + 1))
+    blocks = max(1u, blocks);
     if (count_cells)
         hipLaunchKernelGGL(generic_kernel<true>, dim3(blocks), dim3(kGenericThreads), 0, s, b, st, scratch, stride);
     else
