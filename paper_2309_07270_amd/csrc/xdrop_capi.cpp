@@ -221,6 +221,14 @@ bool validate_host(const xdrop_ctx *c, const xdrop_record &R, std::string &why)
     return true;
 }
 
+// carry pool of a slot: 256 words per record of capacity (the c4 stress mix
+// hands about 0.16 extensions per record to the 2048-slot class, 2,064 words
+// each), at most 64 Mi words; a full pool only makes tasks restart
+uint32_t carry_words_for(uint32_t cap)
+{
+    return (uint32_t)std::min<uint64_t>((uint64_t)cap * 256u, 64ull << 20);
+}
+
 size_t slot_bytes(uint32_t cap)
 {
     const size_t n = cap;
@@ -234,6 +242,8 @@ size_t slot_bytes(uint32_t cap)
     add(2 * n * sizeof(TaskOut));
     add((size_t)kNumClasses * 2 * n * sizeof(uint32_t));   // qbuf
     add((size_t)kNumClasses * 2 * n * sizeof(uint32_t));   // qkey
+    add((size_t)kNumClasses * 2 * n * sizeof(uint32_t));   // qstate
+    add((size_t)carry_words_for(cap) * sizeof(int32_t));   // carry pool
     add(CtrLayout::kWords * sizeof(uint32_t) + 64);
     add((size_t)kNumClasses * kNumBuckets * sizeof(uint32_t));
     add(kStageSumWords * sizeof(unsigned long long));
@@ -280,6 +290,9 @@ void alloc_slot_buffers(xdrop_ctx *c, Slot &s, uint32_t cap)
     s.dev.tout = (TaskOut *)take(2 * n * sizeof(TaskOut));
     s.dev.qbuf = (uint32_t *)take((size_t)kNumClasses * 2 * n * sizeof(uint32_t));
     s.dev.qkey = (uint32_t *)take((size_t)kNumClasses * 2 * n * sizeof(uint32_t));
+    s.dev.qstate = (uint32_t *)take((size_t)kNumClasses * 2 * n * sizeof(uint32_t));
+    s.dev.carry_words = carry_words_for(cap);
+    s.dev.carry = (int32_t *)take((size_t)s.dev.carry_words * sizeof(int32_t));
     s.dev.ctr = (uint32_t *)take(CtrLayout::kWords * sizeof(uint32_t) + 64);
     s.d_n = s.dev.ctr + CtrLayout::kWords;
     s.dev.bucket_hist = (uint32_t *)take((size_t)kNumClasses * kNumBuckets * sizeof(uint32_t));

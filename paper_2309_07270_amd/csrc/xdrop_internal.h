@@ -32,7 +32,8 @@ struct TaskOut {
 enum : uint32_t { kStatusDone = 0, kStatusOverflow = 1 };
 
 // Extension kernels ("classes"), tried in order; a task whose live band
-// outgrows a class restarts in the next one:
+// outgrows a class moves to the next one (a wide class hands over its state
+// when the carry pool has room; otherwise the task restarts there):
 //   0  adaptive register window, 1..4 cells per lane (64..256 slots), the
 //      width following the band;
 //   1  fixed register window of 16 cells per lane (1024 slots);
@@ -58,6 +59,9 @@ struct BatchDev {
     TaskOut *tout;            // 2 per record
     uint32_t *qbuf;           // kNumClasses queues of capacity 2*cap (task ids)
     uint32_t *qkey;           // unsorted queue staging: (task id) per class, capacity 2*cap
+    uint32_t *qstate;         // per queue entry of classes >= 1: word offset of its carried state, or kNoCarry
+    int32_t *carry;           // carried states of extensions handed to a wider class (CarryLayout)
+    uint32_t carry_words;     // capacity of carry, in words
     uint32_t *ctr;            // counters, see CtrLayout
     uint32_t *bucket_hist;    // kNumClasses * kNumBuckets
     unsigned long long *stage_sum;  // kStageSumWords: [0..7] cells, [8..15] tasks, [16..23] slot-steps per stage (1 + class)
@@ -71,7 +75,27 @@ struct CtrLayout {
     static constexpr int kStage = 2 * kNumClasses;         // per class: staging length (bucketing)
     static constexpr int kErrors = 3 * kNumClasses;        // invalid records
     static constexpr int kN = 3 * kNumClasses + 1;         // record count of the batch
-    static constexpr int kWords = 3 * kNumClasses + 2;
+    static constexpr int kCarry = 3 * kNumClasses + 2;     // words of the carry pool handed out
+    static constexpr int kWords = 3 * kNumClasses + 3;
+};
+
+// State of an extension handed from a wide class to the next one: a header,
+// then the live window of anti-diagonals d-1 and d-2, win slots each, in
+// the window's units (Z = S + |gap| * anti-diagonal; dead = below -2^29).
+// Slot k of anti-diagonal e holds cell i = base + floor(e / 2) + k.
+constexpr uint32_t kNoCarry = 0xffffffffu;
+struct CarryLayout {
+    static constexpr int kD = 0;       // next anti-diagonal
+    static constexpr int kBase = 1;
+    static constexpr int kT = 2;       // best score so far and its cell
+    static constexpr int kBi = 3;
+    static constexpr int kBj = 4;
+    static constexpr int kMn = 5;      // live slots over both anti-diagonals
+    static constexpr int kMx = 6;
+    static constexpr int kWin = 7;     // window slots
+    static constexpr int kCells = 8;   // two words each (cell counting)
+    static constexpr int kSlots = 10;
+    static constexpr int kHeader = 16;
 };
 
 struct StoreDev {

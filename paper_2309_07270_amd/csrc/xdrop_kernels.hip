@@ -198,7 +198,8 @@ __global__ void reset_kernel(uint32_t *ctr, uint32_t *hist, unsigned long long *
                              uint32_t n_imm)
 {
     const int t = threadIdx.x;
-    if (t < CtrLayout::kN) ctr[t] = 0;
+    static_assert(CtrLayout::kWords <= 256, "one thread per counter word");
+    if (t < CtrLayout::kWords && t != CtrLayout::kN) ctr[t] = 0;
     if (t == 0) ctr[CtrLayout::kN] = n_src ? *n_src : n_imm;
     if (t < kStageSumWords) stage_sum[t] = 0ull;
     for (int i = t; i < kNumClasses * kNumBuckets; i += blockDim.x) hist[i] = 0;
@@ -916,10 +917,111 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) a
             o.score = s.T; o.i = s.bi; o.j = s.bj; o.status = (uint32_t)cls; o.cells = s.cells; o.slots = s.slots;
             b.tout[t] = o;
         } else {
+            // restarts in the first wide class (adaptive bands reach 256
+            // slots early in an extension, so little work is repeated)
             const uint32_t pos = wave_fetch_add(&b.ctr[CtrLayout::kCount + cls + 1], 1u);
             b.qbuf[(cls + 1) * qcap + pos] = t;
+            b.qstate[(cls + 1) * qcap + pos] = kNoCarry;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Hand-over between classes.  A wide window that overflows stores its state
+// in the carry pool, and the next class resumes from it instead of
+// recomputing the anti-diagonals done so far.
+// ---------------------------------------------------------------------------
+
+// `need` words of the carry pool (wave-uniform offset), or kNoCarry when full
+__device__ __forceinline__ uint32_t carry_alloc(const BatchDev &b, uint32_t need)
+{
+    // a stale read of the counter only costs an add that then fails the bound
+    if ((uint32_t)uni((int)b.ctr[CtrLayout::kCarry]) >= b.carry_words) return kNoCarry;
+    const uint32_t off = wave_fetch_add(&b.ctr[CtrLayout::kCarry], need);
+    return (uint64_t)off + need <= (uint64_t)b.carry_words ? off : kNoCarry;
+}
+
+// the window a wide run saved to LDS (anti-diagonal d-1 at lds[0, WIN), d-2
+// at lds[STRIDE, STRIDE + WIN)) and its state, into the record at `off`
+template <int WIN, int STRIDE>
+__device__ void carry_store(const BatchDev &b, uint32_t off, const XState &s, const int *lds)
+{
+    int32_t *rec = b.carry + off;
+    const int lane = lane_id();
+    for (int k = lane; k < WIN; k += 64) {
+        rec[CarryLayout::kHeader + k] = lds[k];
+        rec[CarryLayout::kHeader + WIN + k] = lds[STRIDE + k];
+    }
+    if (lane == 0) {
+        rec[CarryLayout::kD] = s.d;
+        rec[CarryLayout::kBase] = s.base;
+        rec[CarryLayout::kT] = s.T;
+        rec[CarryLayout::kBi] = s.bi;
+        rec[CarryLayout::kBj] = s.bj;
+        rec[CarryLayout::kMn] = s.mn;
+        rec[CarryLayout::kMx] = s.mx;
+        rec[CarryLayout::kWin] = WIN;
+        rec[CarryLayout::kCells] = (int32_t)(uint32_t)s.cells;
+        rec[CarryLayout::kCells + 1] = (int32_t)(uint32_t)(s.cells >> 32);
+        rec[CarryLayout::kSlots] = (int32_t)(uint32_t)s.slots;
+        rec[CarryLayout::kSlots + 1] = (int32_t)(uint32_t)(s.slots >> 32);
+    }
+}
+
+// wave-uniform header word of a carried state
+__device__ __forceinline__ int carry_word(const int32_t *rec, int k) { return uni(rec[k]); }
+
+__device__ __forceinline__ void carry_state(const int32_t *rec, XState &s)
+{
+    s.d = carry_word(rec, CarryLayout::kD);
+    s.base = carry_word(rec, CarryLayout::kBase);
+    s.T = carry_word(rec, CarryLayout::kT);
+    s.bi = carry_word(rec, CarryLayout::kBi);
+    s.bj = carry_word(rec, CarryLayout::kBj);
+    s.mn = carry_word(rec, CarryLayout::kMn);
+    s.mx = carry_word(rec, CarryLayout::kMx);
+    s.cells = (uint64_t)(uint32_t)carry_word(rec, CarryLayout::kCells) |
+              ((uint64_t)(uint32_t)carry_word(rec, CarryLayout::kCells + 1) << 32);
+    s.slots = (uint64_t)(uint32_t)carry_word(rec, CarryLayout::kSlots) |
+              ((uint64_t)(uint32_t)carry_word(rec, CarryLayout::kSlots + 1) << 32);
+}
+
+// One extension in a fixed wide window: fresh, or resumed from the carried
+// state at `coff` (a narrower window's band, re-centred in this one).  On
+// overflow the state goes to the carry pool; returns kDone or kGrow and sets
+// `out_off` to the record (kNoCarry: none, the task restarts).
+template <int C, bool COUNT, bool MA1, bool SIGF>
+__device__ uint32_t run_wide(const BatchDev &b, const StoreDev &st, const Task &k, int *lds, XState &s,
+                             uint32_t coff, uint32_t &out_off)
+{
+    constexpr int WIN = 64 * C;
+    WideWindow<C, COUNT, MA1, SIGF> w;
+    out_off = kNoCarry;
+    if (coff == kNoCarry) {
+        w.init(s);
+    } else {
+        const int32_t *rec = b.carry + coff;
+        carry_state(rec, s);
+        const int from = carry_word(rec, CarryLayout::kWin);   // < WIN: written by a narrower class
+        for (int q = lane_id(); q < from; q += 64) {
+            lds[q] = rec[CarryLayout::kHeader + q];
+            lds[WIN + q] = rec[CarryLayout::kHeader + from + q];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int width = s.mx - s.mn + 1;
+        const int delta = s.mn - (WIN - width) / 2;
+        s.base += delta;
+        w.load(lds, from, delta);
+    }
+    const uint32_t status = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, lds, s, -1);
+    if (status != kDone) {
+        // the window is in LDS (run saves it before returning kGrow)
+        out_off = carry_alloc(b, CarryLayout::kHeader + 2 * WIN);
+        if (out_off != kNoCarry) carry_store<WIN, WIN>(b, out_off, s, lds);
+    }
+    return status;
 }
 
 // Fixed wide window (C cells per lane) for bands the adaptive kernel cannot hold.
@@ -934,22 +1036,16 @@ __global__ void __launch_bounds__(256) wide_kernel(BatchDev b, StoreDev st, int 
         const uint32_t idx = wave_fetch_add(&b.ctr[CtrLayout::kHead + cls], 1u);
         if (idx >= cnt) break;
         const uint32_t t = (uint32_t)uni((int)b.qbuf[cls * qcap + idx]);
+        const uint32_t coff = (uint32_t)uni((int)b.qstate[cls * qcap + idx]);
         const Task k = load_task(b.recs, st.reads, t);
         XState s;
-        uint32_t status;
-        if (k.ma != 1) {
-            WideWindow<C, COUNT, false, false> w;
-            w.init(s);
-            status = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, lds, s, -1);
-        } else if (sigma_fits_2bits(k)) {
-            WideWindow<C, COUNT, true, true> w;
-            w.init(s);
-            status = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, lds, s, -1);
-        } else {
-            WideWindow<C, COUNT, true, false> w;
-            w.init(s);
-            status = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, lds, s, -1);
-        }
+        uint32_t status, out_off;
+        if (k.ma != 1)
+            status = run_wide<C, COUNT, false, false>(b, st, k, lds, s, coff, out_off);
+        else if (sigma_fits_2bits(k))
+            status = run_wide<C, COUNT, true, true>(b, st, k, lds, s, coff, out_off);
+        else
+            status = run_wide<C, COUNT, true, false>(b, st, k, lds, s, coff, out_off);
         if (status == kDone) {
             TaskOut o;
             o.score = s.T; o.i = s.bi; o.j = s.bj; o.status = (uint32_t)cls; o.cells = s.cells; o.slots = s.slots;
@@ -957,6 +1053,7 @@ __global__ void __launch_bounds__(256) wide_kernel(BatchDev b, StoreDev st, int 
         } else {
             const uint32_t pos = wave_fetch_add(&b.ctr[CtrLayout::kCount + cls + 1], 1u);
             b.qbuf[(cls + 1) * qcap + pos] = t;
+            b.qstate[(cls + 1) * qcap + pos] = out_off;
         }
     }
 }
@@ -1156,17 +1253,65 @@ __device__ bool generic_diags(const uint32_t *__restrict__ W, const Geo &g, int 
     return true;
 }
 
+// Start of an unbounded extension: fresh (only S(0,0) = 0 live), or resumed
+// from a wide window's carried state, its live cells moved into the ring
+// (window units Z = S + |gap| * anti-diagonal back to scores).
+__device__ void generic_start(const BatchDev &b, uint32_t coff, int gap, int *P1, int *P2, GState &s)
+{
+    __shared__ int s_rng[4];
+    const int tid = threadIdx.x;
+    s.prev_dead = false;
+    if (coff == kNoCarry) {
+        s.d = 1; s.lo1 = 0; s.hi1 = 0; s.lo2 = 1; s.hi2 = 0;
+        s.T = 0; s.bi = 0; s.bj = 0; s.cells = 0; s.slots = 0;
+        if (tid == 0) P1[0] = 0;   // anti-diagonal 0: S(0,0) = 0
+        __syncthreads();
+        return;
+    }
+    const int32_t *rec = b.carry + coff;
+    s.d = rec[CarryLayout::kD];
+    s.T = rec[CarryLayout::kT];
+    s.bi = rec[CarryLayout::kBi];
+    s.bj = rec[CarryLayout::kBj];
+    s.cells = (uint64_t)(uint32_t)rec[CarryLayout::kCells] | ((uint64_t)(uint32_t)rec[CarryLayout::kCells + 1] << 32);
+    s.slots = (uint64_t)(uint32_t)rec[CarryLayout::kSlots] | ((uint64_t)(uint32_t)rec[CarryLayout::kSlots + 1] << 32);
+    const int base = rec[CarryLayout::kBase], win = rec[CarryLayout::kWin];
+    if (tid == 0) { s_rng[0] = 0x7fffffff; s_rng[1] = -1; s_rng[2] = 0x7fffffff; s_rng[3] = -1; }
+    __syncthreads();
+    const int G = -gap, d1 = s.d - 1, d2 = s.d - 2;
+    const int o1 = base + (d1 >> 1), o2 = base + (d2 >> 1);   // i of slot 0 (d2 >= 0: a window ran)
+    for (int q = tid; q < win; q += kGenericThreads) {
+        const int z1 = rec[CarryLayout::kHeader + q], z2 = rec[CarryLayout::kHeader + win + q];
+        if (z1 > NEG_HALF) {
+            const int i = o1 + q;   // live cells lie inside the table: i >= 0
+            P1[(uint32_t)i & (kRing - 1)] = z1 - G * d1;
+            atomicMin(&s_rng[0], i);
+            atomicMax(&s_rng[1], i);
+        }
+        if (z2 > NEG_HALF) {
+            const int i = o2 + q;
+            P2[(uint32_t)i & (kRing - 1)] = z2 - G * d2;
+            atomicMin(&s_rng[2], i);
+            atomicMax(&s_rng[3], i);
+        }
+    }
+    __syncthreads();
+    s.lo1 = s_rng[0]; s.hi1 = s_rng[1];
+    s.lo2 = s_rng[2]; s.hi2 = s_rng[3];
+    if (s.lo1 > s.hi1) { s.lo1 = 1; s.hi1 = 0; s.prev_dead = true; }
+    if (s.lo2 > s.hi2) { s.lo2 = 1; s.hi2 = 0; }
+    __syncthreads();   // s_rng read by every thread before another task resets it
+}
+
 template <bool COUNT>
-__device__ void generic_run(const uint32_t *__restrict__ W, const Geo &g, int X, int ma, int mi, int gap,
-                            int *ring, int *G2, int *G1, int *G0, GPart (*part)[kGenericWaves], TaskOut &o)
+__device__ void generic_run(const BatchDev &b, uint32_t coff, const uint32_t *__restrict__ W, const Geo &g, int X,
+                            int ma, int mi, int gap, int *ring, int *G2, int *G1, int *G0,
+                            GPart (*part)[kGenericWaves], TaskOut &o)
 {
     const int tid = threadIdx.x;
     GState s;
-    s.d = 1; s.lo1 = 0; s.hi1 = 0; s.lo2 = 1; s.hi2 = 0;
-    s.T = 0; s.bi = 0; s.bj = 0; s.cells = 0; s.slots = 0; s.prev_dead = false;
     int *P0 = ring, *P1 = ring + kRing, *P2 = ring + 2 * kRing;
-    if (tid == 0) P1[0] = 0;   // anti-diagonal 0: S(0,0) = 0
-    __syncthreads();
+    generic_start(b, coff, gap, P1, P2, s);
     if (!generic_diags<COUNT, true>(W, g, X, ma, mi, gap, P2, P1, P0, s, part)) {
         // the band outgrew the ring: the live cells of the last two
         // anti-diagonals move to global memory
@@ -1197,10 +1342,11 @@ __global__ void __launch_bounds__(kGenericThreads) generic_kernel(BatchDev b, St
         __syncthreads();         // read by every thread before thread 0 writes it again
         if (idx >= cnt) break;   // uniform over the block
         const uint32_t t = b.qbuf[cls * qcap + idx];
+        const uint32_t coff = b.qstate[cls * qcap + idx];
         const Task k = load_task(b.recs, st.reads, t);
         TaskOut o;
-        generic_run<COUNT>(st.words, k.g, k.x, k.ma, k.mi, k.gap, ring, base, base + stride, base + 2 * stride,
-                           part, o);
+        generic_run<COUNT>(b, coff, st.words, k.g, k.x, k.ma, k.mi, k.gap, ring, base, base + stride,
+                           base + 2 * stride, part, o);
         if (threadIdx.x == 0) b.tout[t] = o;
         __syncthreads();         // ring and scratch of this task no longer read before the next one starts
     }

@@ -130,6 +130,41 @@ def test_unbounded_band_wider_than_lds_ring(xd):
     assert_same(res, cells, ref)
 
 
+def test_class_hand_over_pool_overflow(xd):
+    # Every right extension here outgrows the 1024- and 2048-slot windows
+    # (X = 2^30, ~2.3 kb on both sides), so each record hands about 6,200
+    # words of window state to wider classes: far more than a 1,024-record
+    # batch's carry pool holds.  Early tasks resume from their carried
+    # state, later ones restart; both must give the oracle's results.
+    rng = np.random.Generator(np.random.PCG64(44))
+    base = rng.integers(0, 4, 2700).astype(np.uint8)
+    reads, lens = [], []
+    for _ in range(24):
+        r = base[rng.integers(0, 150):].copy()
+        r = r[:rng.integers(2300, r.size + 1)]
+        flip = rng.random(r.size) < 0.12
+        r[flip] = (r[flip] + rng.integers(1, 4, int(flip.sum()))) % 4
+        reads.append(r)
+        lens.append(r.size)
+    off = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    store = W.ReadStore(np.concatenate(reads), off, np.array(lens))
+    n = 200
+    recs = np.zeros(n, W.RECORD_DTYPE)
+    recs["read_a"] = rng.integers(0, 24, n)
+    recs["read_b"] = (recs["read_a"] + rng.integers(1, 24, n)) % 24
+    recs["pos_a"] = rng.integers(0, 20, n)
+    recs["pos_b"] = rng.integers(0, 20, n)
+    recs["k"] = 1
+    recs["x"] = np.where(rng.random(n) < 0.8, 1 << 30, 400)
+    recs["match"], recs["mismatch"], recs["gap"] = 1, -1, -1
+    ref, _ = oracle.batch(store.codes, store.off, store.length, recs)
+    note("class hand-over beyond the carry pool: 200 records, X = 2^30 / 400, ~2.3 kb extensions")
+    with xd.Context(store) as ctx:
+        res, cells, stats = ctx.run(recs, count_cells=True)
+    assert_same(res, cells, ref)
+    assert int(stats["stage_tasks"][4]) > 0   # the unbounded class ran
+
+
 def test_identical_reads_full_length(xd):
     rng = np.random.Generator(np.random.PCG64(5))
     seq = rng.integers(0, 4, 3000).astype(np.uint8)
