@@ -995,9 +995,12 @@ __device__ uint32_t run_wide(const BatchDev &b, const StoreDev &st, const Task &
                              uint32_t coff, uint32_t &out_off)
 {
     constexpr int WIN = 64 * C;
+    // the first wide class takes tasks from the adaptive kernel, which hands
+    // over no state: no resume code there (it would cost that kernel registers)
+    constexpr bool kResumes = C != kWideC[0];
     WideWindow<C, COUNT, MA1, SIGF> w;
     out_off = kNoCarry;
-    if (coff == kNoCarry) {
+    if (!kResumes || coff == kNoCarry) {
         w.init(s);
     } else {
         const int32_t *rec = b.carry + coff;
@@ -1024,9 +1027,12 @@ __device__ uint32_t run_wide(const BatchDev &b, const StoreDev &st, const Task &
     return status;
 }
 
-// Fixed wide window (C cells per lane) for bands the adaptive kernel cannot hold.
+// Fixed wide window (C cells per lane) for bands the adaptive kernel cannot
+// hold.  The 1024-slot window is held to 3 wavefronts per SIMD (168 VGPRs);
+// the 2048-slot one needs the whole register file.
 template <int C, bool COUNT>
-__global__ void __launch_bounds__(256) wide_kernel(BatchDev b, StoreDev st, int cls)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 16 ? 3 : 1)))
+wide_kernel(BatchDev b, StoreDev st, int cls)
 {
     extern __shared__ int lds_wide[];
     int *lds = lds_wide + (threadIdx.x >> 6) * (2 * 64 * C);
