@@ -808,8 +808,6 @@ struct Window {
     }
 };
 
-template <int C, bool COUNT, bool MA1, bool SIGF>
-using WideWindow = Window<C, COUNT, MA1, SIGF, 64 * C>;
 
 // sigma - 2*gap of a match and of a mismatch both in [0, 3]
 __device__ __forceinline__ bool sigma_fits_2bits(const Task &k)
@@ -941,16 +939,15 @@ __device__ __forceinline__ uint32_t carry_alloc(const BatchDev &b, uint32_t need
     return (uint64_t)off + need <= (uint64_t)b.carry_words ? off : kNoCarry;
 }
 
-// the window a wide run saved to LDS (anti-diagonal d-1 at lds[0, WIN), d-2
-// at lds[STRIDE, STRIDE + WIN)) and its state, into the record at `off`
-template <int WIN, int STRIDE>
-__device__ void carry_store(const BatchDev &b, uint32_t off, const XState &s, const int *lds)
+// the window a wide run saved to LDS (anti-diagonal d-1 at lds[0, win), d-2
+// at lds[stride, stride + win)) and its state, into the record at `off`
+__device__ void carry_store(const BatchDev &b, uint32_t off, const XState &s, const int *lds, int win, int stride)
 {
     int32_t *rec = b.carry + off;
     const int lane = lane_id();
-    for (int k = lane; k < WIN; k += 64) {
+    for (int k = lane; k < win; k += 64) {
         rec[CarryLayout::kHeader + k] = lds[k];
-        rec[CarryLayout::kHeader + WIN + k] = lds[STRIDE + k];
+        rec[CarryLayout::kHeader + win + k] = lds[stride + k];
     }
     if (lane == 0) {
         rec[CarryLayout::kD] = s.d;
@@ -960,7 +957,7 @@ __device__ void carry_store(const BatchDev &b, uint32_t off, const XState &s, co
         rec[CarryLayout::kBj] = s.bj;
         rec[CarryLayout::kMn] = s.mn;
         rec[CarryLayout::kMx] = s.mx;
-        rec[CarryLayout::kWin] = WIN;
+        rec[CarryLayout::kWin] = win;
         rec[CarryLayout::kCells] = (int32_t)(uint32_t)s.cells;
         rec[CarryLayout::kCells + 1] = (int32_t)(uint32_t)(s.cells >> 32);
         rec[CarryLayout::kSlots] = (int32_t)(uint32_t)s.slots;
@@ -986,56 +983,123 @@ __device__ __forceinline__ void carry_state(const int32_t *rec, XState &s)
               ((uint64_t)(uint32_t)carry_word(rec, CarryLayout::kSlots + 1) << 32);
 }
 
-// One extension in a fixed wide window: fresh, or resumed from the carried
-// state at `coff` (a narrower window's band, re-centred in this one).  On
-// overflow the state goes to the carry pool; returns kDone or kGrow and sets
-// `out_off` to the record (kNoCarry: none, the task restarts).
-template <int C, bool COUNT, bool MA1, bool SIGF>
-__device__ uint32_t run_wide(const BatchDev &b, const StoreDev &st, const Task &k, int *lds, XState &s,
-                             uint32_t coff, uint32_t &out_off)
+// Window widths (cells per lane) of the two wide classes.  Each class widens
+// and narrows its window along its ladder as the band changes, handing the
+// band over through LDS as the adaptive kernel does; its widest window is
+// the class limit (kWideC).
+template <int L> struct WideLadder;
+template <> struct WideLadder<0> {
+    static constexpr int N = 3;
+    static constexpr int C0 = 8, C1 = 12, C2 = 16;
+};
+template <> struct WideLadder<1> {
+    static constexpr int N = 2;
+    static constexpr int C0 = 24, C1 = 32, C2 = 32;
+};
+static_assert(WideLadder<0>::C2 == kWideC[0] && WideLadder<1>::C1 == kWideC[1], "class limits");
+constexpr int kWideGrowMargin = 32;     // free slots per side after widening
+constexpr int kWideShrinkMargin = 64;   // narrow once the band fits the next smaller window with this slack
+
+template <int L>
+__device__ __forceinline__ int ladder_c(int ci)
 {
-    constexpr int WIN = 64 * C;
+    return ci == 0 ? WideLadder<L>::C0 : ci == 1 ? WideLadder<L>::C1 : WideLadder<L>::C2;
+}
+
+// smallest rung whose window holds `width` slots with `margin` free on each side; -1 if none
+template <int L>
+__device__ __forceinline__ int ladder_fit(int width, int margin)
+{
+    for (int ci = 0; ci < WideLadder<L>::N; ++ci)
+        if (width + 2 * margin <= 64 * ladder_c<L>(ci)) return ci;
+    return -1;
+}
+
+// One extension in wide class L: fresh, or resumed from the state a
+// narrower class carried over (its band re-centred in the rung that fits).
+// When the band outgrows the widest rung the state goes to the carry pool;
+// returns kDone or kGrow and sets `out_off` to the record (kNoCarry: none,
+// the task restarts in the next class).
+template <int L, bool COUNT, bool MA1, bool SIGF>
+__device__ uint32_t run_ladder(const BatchDev &b, const StoreDev &st, const Task &k, int *lds, XState &s,
+                               uint32_t coff, uint32_t &out_off)
+{
+    using LD = WideLadder<L>;
+    constexpr int STRIDE = 64 * kWideC[L];
+    out_off = kNoCarry;
+    int ci = 0, from_win = 0, delta = 0;
+    bool fresh = true;
     // the first wide class takes tasks from the adaptive kernel, which hands
     // over no state: no resume code there (it would cost that kernel registers)
-    constexpr bool kResumes = C != kWideC[0];
-    WideWindow<C, COUNT, MA1, SIGF> w;
-    out_off = kNoCarry;
-    if (!kResumes || coff == kNoCarry) {
-        w.init(s);
-    } else {
+    if (L > 0 && coff != kNoCarry) {
         const int32_t *rec = b.carry + coff;
         carry_state(rec, s);
-        const int from = carry_word(rec, CarryLayout::kWin);   // < WIN: written by a narrower class
-        for (int q = lane_id(); q < from; q += 64) {
+        from_win = carry_word(rec, CarryLayout::kWin);   // a narrower class's window: fits this stride
+        for (int q = lane_id(); q < from_win; q += 64) {
             lds[q] = rec[CarryLayout::kHeader + q];
-            lds[WIN + q] = rec[CarryLayout::kHeader + from + q];
+            lds[STRIDE + q] = rec[CarryLayout::kHeader + from_win + q];
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const int width = s.mx - s.mn + 1;
-        const int delta = s.mn - (WIN - width) / 2;
+        ci = ladder_fit<L>(width, kWideGrowMargin);
+        if (ci < 0) ci = LD::N - 1;   // width <= from_win < the widest rung - 4
+        delta = s.mn - (64 * ladder_c<L>(ci) - width) / 2;
         s.base += delta;
-        w.load(lds, from, delta);
+        fresh = false;
     }
-    const uint32_t status = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, lds, s, -1);
-    if (status != kDone) {
-        // the window is in LDS (run saves it before returning kGrow)
-        out_off = carry_alloc(b, CarryLayout::kHeader + 2 * WIN);
-        if (out_off != kNoCarry) carry_store<WIN, WIN>(b, out_off, s, lds);
+    for (;;) {
+        const int shrink_width = ci > 0 ? 64 * ladder_c<L>(ci - 1) - 2 * kWideShrinkMargin : -1;
+        uint32_t stt = kDone;
+        if (ci == 0) {
+            Window<LD::C0, COUNT, MA1, SIGF, STRIDE> w;
+            if (fresh) w.init(s); else w.load(lds, from_win, delta);
+            stt = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
+        } else if (LD::N == 2 || ci == 1) {
+            Window<LD::C1, COUNT, MA1, SIGF, STRIDE> w;
+            w.load(lds, from_win, delta);
+            stt = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
+        } else {
+            if constexpr (LD::N > 2) {
+                Window<LD::C2, COUNT, MA1, SIGF, STRIDE> w;
+                w.load(lds, from_win, delta);
+                stt = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
+            }
+        }
+        if (stt == kDone) return kDone;
+        fresh = false;
+        const int width = s.mx - s.mn + 1;
+        const int cur = 64 * ladder_c<L>(ci);
+        int nci = ci - 1;   // kShrink
+        if (stt == kGrow) {
+            // width + 4 > cur, so any fitting rung is wider than this one
+            nci = ladder_fit<L>(width, kWideGrowMargin);
+            if (nci < 0) nci = ladder_fit<L>(width, 2);
+            if (nci < 0) {
+                // the window (saved in LDS by run) goes to the next class
+                out_off = carry_alloc(b, CarryLayout::kHeader + 2 * cur);
+                if (out_off != kNoCarry) carry_store(b, out_off, s, lds, cur, STRIDE);
+                return kGrow;
+            }
+        }
+        from_win = cur;
+        delta = s.mn - (64 * ladder_c<L>(nci) - width) / 2;
+        s.base += delta;
+        ci = nci;
     }
-    return status;
 }
 
-// Fixed wide window (C cells per lane) for bands the adaptive kernel cannot
-// hold.  The 1024-slot window is held to 3 wavefronts per SIMD (168 VGPRs);
-// the 2048-slot one needs the whole register file.
-template <int C, bool COUNT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C <= 16 ? 3 : 1)))
+// Wide class L for bands the adaptive kernel cannot hold.  The first class
+// (up to 1024 slots) runs 2 wavefronts per SIMD (256 VGPRs, no spills); the
+// second (up to 2048 slots) needs the whole register file.
+template <int L, bool COUNT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(L == 0 ? 2 : 1)))
 wide_kernel(BatchDev b, StoreDev st, int cls)
 {
+    constexpr int STRIDE = 64 * kWideC[L];
     extern __shared__ int lds_wide[];
-    int *lds = lds_wide + (threadIdx.x >> 6) * (2 * 64 * C);
+    int *lds = lds_wide + (threadIdx.x >> 6) * (2 * STRIDE);
     const uint32_t qcap = 2u * b.cap;
     const uint32_t cnt = b.ctr[CtrLayout::kCount + cls];
     for (;;) {
@@ -1047,11 +1111,11 @@ wide_kernel(BatchDev b, StoreDev st, int cls)
         XState s;
         uint32_t status, out_off;
         if (k.ma != 1)
-            status = run_wide<C, COUNT, false, false>(b, st, k, lds, s, coff, out_off);
+            status = run_ladder<L, COUNT, false, false>(b, st, k, lds, s, coff, out_off);
         else if (sigma_fits_2bits(k))
-            status = run_wide<C, COUNT, true, true>(b, st, k, lds, s, coff, out_off);
+            status = run_ladder<L, COUNT, true, true>(b, st, k, lds, s, coff, out_off);
         else
-            status = run_wide<C, COUNT, true, false>(b, st, k, lds, s, coff, out_off);
+            status = run_ladder<L, COUNT, true, false>(b, st, k, lds, s, coff, out_off);
         if (status == kDone) {
             TaskOut o;
             o.score = s.T; o.i = s.bi; o.j = s.bj; o.status = (uint32_t)cls; o.cells = s.cells; o.slots = s.slots;
@@ -1446,24 +1510,24 @@ void launch_adaptive(const BatchDev &b, const StoreDev &st, const Tuning &tu, ui
         hipLaunchKernelGGL(adaptive_kernel<false>, dim3(blocks), dim3(256), 0, s, b, st, tu.grow_margin, tu.shrink_margin);
 }
 
-template <int C>
+template <int L>
 static void launch_wide_c(const BatchDev &b, const StoreDev &st, int cls, uint32_t grid_waves, bool count,
                           hipStream_t s)
 {
     const uint32_t blocks = (grid_waves + 3) / 4;
-    const size_t lds = 4 * 2 * 64 * C * sizeof(int);
+    const size_t lds = 4 * 2 * 64 * kWideC[L] * sizeof(int);
     if (count)
-        hipLaunchKernelGGL((wide_kernel<C, true>), dim3(blocks), dim3(256), lds, s, b, st, cls);
+        hipLaunchKernelGGL((wide_kernel<L, true>), dim3(blocks), dim3(256), lds, s, b, st, cls);
     else
-        hipLaunchKernelGGL((wide_kernel<C, false>), dim3(blocks), dim3(256), lds, s, b, st, cls);
+        hipLaunchKernelGGL((wide_kernel<L, false>), dim3(blocks), dim3(256), lds, s, b, st, cls);
 }
 
 void launch_wide(int which, const BatchDev &b, const StoreDev &st, uint32_t grid_waves, bool count_cells,
                  hipStream_t s)
 {
-    static_assert(kWideC[0] == 16 && kWideC[1] == 32, "wide classes");
-    if (which == 0) launch_wide_c<16>(b, st, 1 + which, grid_waves, count_cells, s);
-    else launch_wide_c<32>(b, st, 1 + which, grid_waves, count_cells, s);
+    static_assert(kWideClasses == 2, "wide classes");
+    if (which == 0) launch_wide_c<0>(b, st, 1 + which, grid_waves, count_cells, s);
+    else launch_wide_c<1>(b, st, 1 + which, grid_waves, count_cells, s);
 }
 
 void launch_generic(const BatchDev &b, const StoreDev &st, int32_t *scratch, uint64_t stride, uint32_t blocks,
