@@ -36,12 +36,14 @@ enum : uint32_t { kStatusDone = 0, kStatusOverflow = 1 };
 // when the carry pool has room; otherwise the task restarts there):
 //   0  adaptive register window, 1..4 cells per lane (64..256 slots), the
 //      width following the band;
-//   1  fixed register window of 16 cells per lane (1024 slots);
-//   2  fixed register window of 32 cells per lane (2048 slots);
-//   3  unbounded band, anti-diagonals in global memory.
+//   1  register window of 8, 12 or 16 cells per lane (512..1024 slots), the
+//      width following the band;
+//   2  register window of 24 or 32 cells per lane (1536..2048 slots);
+//   3  unbounded band: one workgroup per extension, anti-diagonals in an LDS
+//      ring (global memory beyond 8192 cells).
 constexpr int kAdaptiveClass = 0;
 constexpr int kWideClasses = 2;
-constexpr int kWideC[kWideClasses] = {16, 32};
+constexpr int kWideC[kWideClasses] = {16, 32};   // widest window of each wide class, cells per lane
 constexpr int kGenericClass = 1 + kWideClasses;
 constexpr int kNumClasses = kGenericClass + 1;
 constexpr int kNumStages = kNumClasses + 2;   // ingest, classes..., finalize

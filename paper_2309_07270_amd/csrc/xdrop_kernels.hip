@@ -10,8 +10,8 @@
 //
 // Layout on the device:
 //   * reads: 2 bits per base, both orientations, in one word array;
-//   * one wavefront runs one extension (task); all control is wave-uniform
-//     and lives in SGPRs;
+//   * in the window kernels one wavefront runs one extension (task); all
+//     control is wave-uniform and lives in SGPRs;
 //   * window kernels: the live band of anti-diagonals d-1 and d-2 is held in
 //     VGPRs, 64 lanes x C cells, indexed by slot s = C*lane + r with
 //     i = o_d + s and o_d = base + floor(d/2).  With that origin the diagonal
@@ -27,8 +27,11 @@
 //     the even anti-diagonal of a pair has a live cell in an edge slot, which
 //     keeps every candidate inside the window.  At one cell per lane a half
 //     runs unrolled without tests and is rerun with them if an edge slot went
-//     live.  A band that outgrows the window moves to a wider window or class;
-//   * generic kernel: three anti-diagonals in global memory, any band width.
+//     live.  A band that outgrows the window moves to a wider window through
+//     LDS, or to the next class, which resumes from its carried state;
+//   * unbounded kernel: one workgroup per extension, the last three
+//     anti-diagonals in an LDS ring indexed by i (global memory for bands
+//     wider than the ring), any band width.
 #include <hip/hip_runtime.h>
 
 #include "xdrop_internal.h"
