@@ -29,8 +29,6 @@ struct TaskOut {
     uint64_t slots;    // window lanes stepped over: slot-steps of the window (cell counting only)
 };
 
-enum : uint32_t { kStatusDone = 0, kStatusOverflow = 1 };
-
 // Extension kernels ("classes"), tried in order; a task whose live band
 // outgrows a class moves to the next one (a wide class hands over its state
 // when the carry pool has room; otherwise the task restarts there):

@@ -61,11 +61,6 @@ __device__ __forceinline__ uint32_t wave_fetch_add(uint32_t *p, uint32_t v)
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)old);
 }
 
-__device__ __forceinline__ uint32_t code_at(const uint32_t *__restrict__ W, uint64_t p)
-{
-    return (W[p >> 4] >> ((p & 15) * 2)) & 3u;
-}
-
 // bases p .. p+15 as 2-bit fields (base p in bits 0-1); reads one word past
 // the base p+15 at most, which the store's guard words cover
 __device__ __forceinline__ uint32_t codes16_at(const uint32_t *__restrict__ W, uint64_t p)
