@@ -189,6 +189,21 @@ def main():
     res_t = d_out.cpu().numpy().view(W.RESULT_DTYPE)
     stable = bool(np.array_equal(res_t, res_gpu))
     log(f"persistent (graph): {ms_per_step:.2f} ms/step, {gcups:.1f} GCUPS")
+    # the same batch submitted from host memory, results back to host memory
+    # (PCIe both ways, pinned staging in the library): reported beside the
+    # value, never as it
+    host_submit = None
+    if not args.kernel_only:   # profiling runs keep the dispatch list of the device path
+        h_steps = max(3, args.steps // 4)
+        ctx.run(recs)
+        t_h = time.perf_counter()
+        for _ in range(h_steps):
+            res_h, _, _ = ctx.run(recs)
+        el_h = time.perf_counter() - t_h
+        host_submit = {"gcups": round(total_cells * h_steps / el_h / 1e9, 2),
+                       "ms_per_batch": round(el_h * 1e3 / h_steps, 3), "batches": h_steps,
+                       "results_equal": bool(np.array_equal(res_h, res_gpu))}
+        log(f"host-submitted batches: {host_submit['ms_per_batch']:.2f} ms/batch, {host_submit['gcups']:.1f} GCUPS")
     ctx.close()
 
     # the same kernel sequence launched directly with HIP events between the
@@ -243,7 +258,8 @@ def main():
                                              "stage_ms": dict(zip(X.STAGE_NAMES, np.round(stage_ms, 4).tolist())),
                                              "stage_cells": dict(zip(X.STAGE_NAMES, [int(v) for v in stage_cells])),
                                              "stage_tasks": dict(zip(X.STAGE_NAMES, [int(v) for v in stage_tasks])),
-                                             "stage_slots": dict(zip(X.STAGE_NAMES, [int(v) for v in stage_slots]))}},
+                                             "stage_slots": dict(zip(X.STAGE_NAMES, [int(v) for v in stage_slots]))},
+                       "host_submit": host_submit},
            "roofline": roofline}
 
     if args.kernel_only:

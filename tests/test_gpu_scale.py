@@ -115,3 +115,13 @@ def test_c4b_full_size(xd):
     res, cells, st = run_device(xd, wl, xd.MODE_PERSISTENT)
     check_properties(wl, res)
     check_sample(wl, res, cells, 200, 4)
+
+
+def test_c4_full_size(xd):
+    # the whole 2M-pair mix under +1/-1/-1: the unrelated half runs to a read
+    # end with wide bands (~10^7 cells per record), through every class
+    wl = W.make_workload("c4")
+    note(f"c4 full size: {len(wl.records)} records")
+    res, cells, st = run_device(xd, wl, xd.MODE_PERSISTENT)
+    check_properties(wl, res)
+    check_sample(wl, res, cells, 60, 5)
