@@ -72,6 +72,48 @@ def test_alone_equals_mixed(xd, wl):
         assert np.array_equal(a[0], m[0]) and np.array_equal(a[1], m[1]), f"batch {i} differs"
 
 
+def test_wide_bands_alone_equals_mixed(xd):
+    # c4 stress mix (half unrelated pairs, X = 100, reads up to 100 kb): the
+    # unrelated extensions climb through the wide classes and hand their
+    # state over in each slot's own carry pool while other batches run
+    wl4 = W.make_workload("c4", pairs=3000, genome=1_000_000, coverage=30)
+    rng = np.random.default_rng(4)
+    n_prod, per = 6, 2
+    sizes = rng.integers(150, 300, size=n_prod * per)
+    starts = rng.integers(0, len(wl4.records) - 300, size=n_prod * per)
+    batches = [wl4.records[s:s + z] for s, z in zip(starts, sizes)]
+    note(f"wide bands alone: {len(batches)} batches of the c4 mix one at a time")
+    alone, wide_tasks = [], 0
+    with xd.Context(wl4.store, max_inflight=1) as ctx:
+        for b in batches:
+            res, cells, st = ctx.run(b, count_cells=True)
+            alone.append((res, cells))
+            wide_tasks += int(st["stage_tasks"][3]) + int(st["stage_tasks"][4])
+    assert wide_tasks > 0   # extensions finished after a hand-over
+    note("wide bands mixed: 6 producer threads, 4 slots in flight")
+    mixed = [None] * len(batches)
+    errors = []
+    with xd.Context(wl4.store, max_inflight=4) as ctx:
+        def producer(p):
+            try:
+                for k in range(per):
+                    i = p * per + k
+                    t, out, cells = ctx.submit(batches[i], count_cells=True)
+                    ctx.wait(t)
+                    mixed[i] = (out, cells)
+            except Exception as e:  # pragma: no cover - reported below
+                errors.append(e)
+        th = [threading.Thread(target=producer, args=(p,)) for p in range(n_prod)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join(timeout=120)
+    assert not errors, errors
+    for i, (a, m) in enumerate(zip(alone, mixed)):
+        assert m is not None, f"batch {i} missing"
+        assert np.array_equal(a[0], m[0]) and np.array_equal(a[1], m[1]), f"batch {i} differs"
+
+
 def test_admission_backpressure_and_timeouts(xd, wl):
     recs = wl.records[:20000]
     big = np.tile(wl.records, 20)[:1 << 20]
