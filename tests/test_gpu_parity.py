@@ -165,6 +165,32 @@ def test_class_hand_over_pool_overflow(xd):
     assert int(stats["stage_tasks"][4]) > 0   # the unbounded class ran
 
 
+def test_bands_widen_then_narrow(xd):
+    # A random 2.5-3.2 kb prefix, then 6 kb shared by every read.  Through
+    # the random part the band widens (up to 770-3050 cells for X = 150 ..
+    # 2000): the wide windows step up their ladders and hand over to wider
+    # classes.  In the shared part the band collapses to about X, so the
+    # windows step back down their ladders.
+    rng = np.random.Generator(np.random.PCG64(55))
+    shared = rng.integers(0, 4, 6000).astype(np.uint8)
+    reads = [np.concatenate([rng.integers(0, 4, n).astype(np.uint8), shared]) for n in (2500, 2600, 3200, 3000)]
+    lens = [r.size for r in reads]
+    store = W.ReadStore(np.concatenate(reads), np.concatenate([[0], np.cumsum(lens)[:-1]]), np.array(lens))
+    recs = np.zeros(6, W.RECORD_DTYPE)
+    recs["read_a"] = [0, 0, 2, 1, 0, 2]
+    recs["read_b"] = [1, 1, 3, 3, 3, 1]
+    recs["k"] = 1
+    recs["x"] = [150, 300, 300, 600, 1000, 2000]
+    recs["match"], recs["mismatch"], recs["gap"] = 1, -1, -1
+    ref, _ = oracle.batch(store.codes, store.off, store.length, recs)
+    note("bands that widen through every window class, then narrow")
+    with xd.Context(store) as ctx:
+        res, cells, st = ctx.run(recs, count_cells=True)
+    assert_same(res, cells, ref)
+    tasks = [int(v) for v in st["stage_tasks"]]
+    assert tasks[2] > 0 and tasks[3] > 0 and tasks[4] > 0, tasks
+
+
 def test_identical_reads_full_length(xd):
     rng = np.random.Generator(np.random.PCG64(5))
     seq = rng.integers(0, 4, 3000).astype(np.uint8)
