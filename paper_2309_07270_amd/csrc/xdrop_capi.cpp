@@ -174,7 +174,7 @@ Tuning default_tuning()
     t.shrink_margin = 6;
     t.waves_per_cu = 32;
     t.buckets = 1;
-    t.generic_waves = 64;
+    t.generic_waves = 64 * kGenericBlockWaves;   // 64 extensions of unbounded band at once
     return t;
 }
 
