@@ -270,6 +270,19 @@ void free_slot_buffers(Slot &s)
     s.bytes = 0;
 }
 
+// Unbounded-kernel workgroups of a slot: the tuned count, fewer when the
+// reads are so long that their scratch (three anti-diagonals of the longest
+// read per workgroup, used only by bands wider than the LDS ring) would pass
+// 256 MiB
+uint64_t scratch_stride_of(const xdrop_ctx *c) { return ((uint64_t)c->st.max_len + 2 + 63) & ~uint64_t(63); }
+
+uint32_t slot_generic_blocks(const xdrop_ctx *c)
+{
+    const uint64_t per_block = 3 * scratch_stride_of(c) * sizeof(int32_t);
+    const uint64_t fit = std::max<uint64_t>(1, (256ull << 20) / per_block);
+    return (uint32_t)std::min<uint64_t>(generic_blocks(c->tune.generic_waves), fit);
+}
+
 void alloc_slot_buffers(xdrop_ctx *c, Slot &s, uint32_t cap)
 {
     s.cap = cap;
@@ -299,8 +312,8 @@ void alloc_slot_buffers(xdrop_ctx *c, Slot &s, uint32_t cap)
     s.dev.stage_sum = (unsigned long long *)take(kStageSumWords * sizeof(unsigned long long));
     s.dev.cap = cap;
     // unbounded-kernel scratch: three anti-diagonals per workgroup
-    s.generic_blocks = generic_blocks(c->tune.generic_waves);
-    s.scratch_stride = ((uint64_t)c->st.max_len + 2 + 63) & ~uint64_t(63);
+    s.generic_blocks = slot_generic_blocks(c);
+    s.scratch_stride = scratch_stride_of(c);
     HIP_TRY(hipMalloc(&s.scratch, (size_t)s.generic_blocks * 3 * s.scratch_stride * sizeof(int32_t)));
     s.bytes += (size_t)s.generic_blocks * 3 * s.scratch_stride * sizeof(int32_t);
     HIP_TRY(hipHostMalloc((void **)&s.h_recs, n * sizeof(xdrop_record), hipHostMallocDefault));
@@ -318,8 +331,7 @@ void alloc_slot_buffers(xdrop_ctx *c, Slot &s, uint32_t cap)
 
 size_t slot_footprint(const xdrop_ctx *c, uint32_t cap)
 {
-    const uint64_t stride = ((uint64_t)c->st.max_len + 2 + 63) & ~uint64_t(63);
-    return slot_bytes(cap) + (size_t)generic_blocks(c->tune.generic_waves) * 3 * stride * sizeof(int32_t);
+    return slot_bytes(cap) + (size_t)slot_generic_blocks(c) * 3 * scratch_stride_of(c) * sizeof(int32_t);
 }
 
 uint32_t round_cap(size_t n)
