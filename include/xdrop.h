@@ -79,15 +79,20 @@ enum {
 };
 
 /* Kernel stages reported in xdrop_batch_stats.stage_ms / stage_cells.  An
- * extension runs in the adaptive kernel first and restarts in the next
- * stage only when its live band outgrows the current one. */
+ * extension runs in the adaptive kernel first and moves to the next stage
+ * only when its live band outgrows the current one: out of the adaptive
+ * kernel it restarts from the seed; between the later stages it carries its
+ * state over (restarting only when the batch's carry pool is full). */
 enum {
     XDROP_STAGE_INGEST = 0,       /* counter reset, validation, seed, bucketing  */
     XDROP_STAGE_ADAPTIVE = 1,     /* register window of 64..256 slots that
                                      follows the band width                 */
-    XDROP_STAGE_WIDE1024 = 2,     /* register window of 1024 slots          */
-    XDROP_STAGE_WIDE2048 = 3,     /* register window of 2048 slots          */
-    XDROP_STAGE_GENERIC = 4,      /* unbounded band (global memory)         */
+    XDROP_STAGE_WIDE1024 = 2,     /* register window of 512..1024 slots that
+                                     follows the band width                 */
+    XDROP_STAGE_WIDE2048 = 3,     /* register window of 1536..2048 slots    */
+    XDROP_STAGE_GENERIC = 4,      /* unbounded band: one workgroup per
+                                     extension, LDS ring (global memory for
+                                     bands over 8192 cells)                 */
     XDROP_STAGE_FINALIZE = 5,     /* result write-back                      */
     XDROP_NUM_STAGES = 6
 };
