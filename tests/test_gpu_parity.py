@@ -75,13 +75,24 @@ def small_case(seed, n_reads, lo, hi, n_recs, x_choices):
     return store, recs, ref
 
 
-@pytest.mark.parametrize("seed,lo,hi,xs", [
-    (11, 1, 40, (0, 1, 2, 3, 5)),
-    (12, 20, 400, (0, 5, 20, 50)),
-    (13, 300, 1500, (10, 50, 100)),
+@pytest.mark.parametrize("seed,lo,hi,xs,related,n_recs", [
+    (11, 1, 40, (0, 1, 2, 3, 5), 0.0, 3000),
+    (12, 20, 400, (0, 5, 20, 50), 0.0, 3000),
+    (13, 300, 1500, (10, 50, 100), 0.0, 3000),
+    # wide bands: about two thirds of these extensions leave the adaptive
+    # kernel, hundreds reach the 2048-slot class by hand-over, a few the
+    # unbounded kernel
+    (102, 800, 3000, (500, 1500, 1 << 30), 0.7, 1500),
+    (103, 2000, 3000, (50, 1000, 3000), 0.7, 1500),
 ])
-def test_random_records_bit_exact(xd, seed, lo, hi, xs):
-    store, recs, ref = small_case(seed, 60, lo, hi, 3000, xs)
+def test_random_records_bit_exact(xd, seed, lo, hi, xs, related, n_recs):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if related:
+        store = W.random_store(rng, 40, lo, hi, related=related)
+        recs = W.random_records(rng, store, n_recs, x_choices=xs)
+        ref, _ = oracle.batch(store.codes, store.off, store.length, recs)
+    else:
+        store, recs, ref = small_case(seed, 60, lo, hi, n_recs, xs)
     note(f"random records seed={seed} len=[{lo},{hi}] X={xs}")
     for mode in (0, 1):
         with xd.Context(store, mode=mode) as ctx:
