@@ -78,14 +78,50 @@ def read_traffic(stage_name: str, workload: str):
     return float(m_bytes.group(1))
 
 
+WORKLOAD_TEXT = {
+    "c0": "read pairs, 200 kb genome at 30x, reads U[1,2] kb, 15% error, k=17, X=50, +1/-1/-1",
+    "c1": "read pairs, 29x-shaped 4.6 Mb genome, reads lognormal mean 8 kb sd 4 kb [1,30] kb, 15% error "
+          "(8/4/3 sub/ins/del), one planted exact 17-mer seed per pair, X=50, +1/-1/-1",
+    "c2": "read pairs of uneven length, 100x-shaped 4.6 Mb genome, reads lognormal mean 10 kb sd 5 kb "
+          "[1,40] kb, 15% error (8/4/3 sub/ins/del), one planted exact 17-mer seed per pair, X drawn per pair "
+          "from {20,50,100}, +1/-1/-1; the whole batch in one hipGraph launch",
+    "c4": "pairs: half true overlaps (100x, reads lognormal mean 20 kb sd 10 kb [1,100] kb, 15% error), "
+          "half unrelated pairs against a 50,000-read decoy pool; X=100, +1/-1/-1",
+    "c4b": "pairs: half true overlaps (100x, reads lognormal mean 20 kb sd 10 kb [1,100] kb, 15% error), "
+           "half unrelated pairs against a 50,000-read decoy pool; X=100, +1/-2/-2",
+}
+
+
+def host_cpu():
+    """CPU model, logical CPUs of the host and CPUs this process may use."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity": allowed}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--workload", default="c2")
     ap.add_argument("--pairs", type=int, default=None, help="shrink the workload (tests only)")
-    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--plain-steps", type=int, default=20, help="passes of the plain form over the batch")
+    ap.add_argument("--small-batch-passes", type=int, default=5,
+                    help="passes of 10,000-record batches through the persistent form")
+    ap.add_argument("--tune-sample", type=int, default=200000,
+                    help="records the autotuner runs on (the first ones of the batch)")
+    ap.add_argument("--no-side-c1", action="store_true", help="skip the c1 side measurement")
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-only", action="store_true",
@@ -95,6 +131,8 @@ def main():
     ap.add_argument("--serve", action="store_true",
                     help="serving loop: 25 producers, Poisson arrivals, swept offered load (c3 / c4)")
     ap.add_argument("--serve-seconds", type=float, default=6.0)
+    ap.add_argument("--serve-min-batches", type=int, default=0,
+                    help="serving: extend a load point until it has completed this many batches")
     ap.add_argument("--serve-points", default="0.1,0.3,0.5,0.7,0.9,1.0,1.1,1.2")
     ap.add_argument("--producers", type=int, default=25)
     ap.add_argument("--seeds", action="store_true",
@@ -148,8 +186,8 @@ def main():
     d_cells = torch.zeros(n, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
 
-    # autotuner (untimed): launch parameters chosen on the whole batch (every
-    # setting gives the same results), or taken from a tuning file
+    # autotuner (untimed): launch parameters chosen on the first records of
+    # the batch (every setting gives the same results), or taken from a file
     t0 = time.time()
     if args.tuning_cache and os.path.exists(args.tuning_cache):
         ctx = X.Context(wl.store, mode=X.MODE_PERSISTENT, tuning_cache=args.tuning_cache)
@@ -157,8 +195,9 @@ def main():
         log(f"tuning from {args.tuning_cache}: {tuning}")
     else:
         ctx = X.Context(wl.store, mode=X.MODE_PERSISTENT)
-        tuning, tune_ms = ctx.autotune(recs, cache_path=args.tuning_cache)
-        log(f"autotune: {tuning} ({tune_ms:.2f} ms per batch, {time.time() - t0:.1f}s)")
+        tuning, tune_ms = ctx.autotune(recs[:args.tune_sample], cache_path=args.tuning_cache)
+        log(f"autotune on {min(n, args.tune_sample)} records: {tuning} ({tune_ms:.2f} ms per sample batch, "
+            f"{time.time() - t0:.1f}s)")
     # counting pass (untimed): exact candidate cells of every extension
     t = ctx.submit_device(d_recs, n, d_out, d_cells, stream=stream)
     ctx.wait(t)
@@ -182,18 +221,38 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t_start, lat, stage / max(steps, 1)
 
-    # timed persistent steps: the captured graph (headline value)
+    chunk = 10000
+
+    def chunked(c, passes):
+        """The batch as sequential 10,000-record requests: per-request
+        latencies, per-pass times and the total time."""
+        lat, per_pass = [], []
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(passes):
+            p0 = time.perf_counter()
+            for off in range(0, n, chunk):
+                m = min(chunk, n - off)
+                s0 = time.perf_counter()
+                c.wait(c.submit_device(d_recs[off * 32:(off + m) * 32], m, d_out[off * 32:(off + m) * 32], None,
+                                       stream=stream))
+                lat.append((time.perf_counter() - s0) * 1e3)
+            per_pass.append((time.perf_counter() - p0) * 1e3)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t_start, lat, per_pass
+
+    # timed persistent steps: the whole batch per captured-graph launch (headline value)
     elapsed, lat, _ = timed(ctx, args.steps, args.warmup)
     ms_per_step = elapsed * 1e3 / args.steps
     gcups = total_cells * args.steps / elapsed / 1e9
     res_t = d_out.cpu().numpy().view(W.RESULT_DTYPE)
     stable = bool(np.array_equal(res_t, res_gpu))
     log(f"persistent (graph): {ms_per_step:.2f} ms/step, {gcups:.1f} GCUPS")
-    # the same batch submitted from host memory, results back to host memory
-    # (PCIe both ways, pinned staging in the library): reported beside the
-    # value, never as it
-    host_submit = None
+    host_submit = small = None
     if not args.kernel_only:   # profiling runs keep the dispatch list of the device path
+        # the same batch submitted from host memory, results back to host
+        # memory (PCIe both ways, pinned staging in the library): reported
+        # beside the value, never as it
         h_steps = max(3, args.steps // 4)
         ctx.run(recs)
         t_h = time.perf_counter()
@@ -204,6 +263,15 @@ def main():
                        "ms_per_batch": round(el_h * 1e3 / h_steps, 3), "batches": h_steps,
                        "results_equal": bool(np.array_equal(res_h, res_gpu))}
         log(f"host-submitted batches: {host_submit['ms_per_batch']:.2f} ms/batch, {host_submit['gcups']:.1f} GCUPS")
+        # the same records as 10,000-record requests through the persistent form
+        chunked(ctx, 1)   # warm-up
+        s_el, s_lat, _ = chunked(ctx, args.small_batch_passes)
+        res_s = d_out.cpu().numpy().view(W.RESULT_DTYPE)
+        small = {"gcups": round(total_cells * args.small_batch_passes / s_el / 1e9, 2),
+                 "p50_ms": pct(s_lat, 50), "p99_ms": pct(s_lat, 99), "batch_records": chunk,
+                 "batches": len(s_lat), "results_equal_whole": bool(np.array_equal(res_s, res_gpu))}
+        log(f"persistent, 10k requests: {small['gcups']:.1f} GCUPS, p50 {small['p50_ms']:.2f} ms, "
+            f"p99 {small['p99_ms']:.2f} ms")
     ctx.close()
 
     # the same kernel sequence launched directly with HIP events between the
@@ -240,20 +308,19 @@ def main():
                 # secondary bound: cells / window lane-steps of the kernel's extensions
                 "lane_occupancy": stage_cells[dom] / stage_slots[dom] if stage_slots[dom] else None}
 
+    text = WORKLOAD_TEXT.get(args.workload, "records")
     out = {"metric": "X-drop GCUPS + alignments/s on 1 GPU, batched vs plain; p50/p99 latency",
            "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "int32",
            "data": "synthetic (seeded generator; E. coli-shaped)",
-           "config": {"workload": f"{args.workload}: {n} read pairs, 29x-shaped 4.6 Mb genome, reads lognormal "
-                                  f"mean 8 kb sd 4 kb [1,30] kb, 15% error, k=17, X=50, +1/-1/-1"
-                      if args.workload == "c1" else f"{args.workload}: {n} records",
-                      "records": n, "cells_per_step": total_cells, "form": "persistent+hipGraph",
-                      "tuning": tuning,
-                      "parallelism": "1 GPU"},
+           "config": {"workload": f"{args.workload}: {n:,} {text}", "records": n,
+                      "cells_per_step": total_cells, "form": "persistent+hipGraph",
+                      "tuning": tuning, "parallelism": "1 GPU"},
            "alignments_per_s": round(n * args.steps / elapsed, 1),
            "batched": {"gcups": round(gcups, 2), "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
                        "batch_records": n, "results_stable_across_steps": stable,
+                       "requests_10k": small,
                        "profiled_launches": {"gcups": round(p_gcups, 2),
                                              "stage_ms": dict(zip(X.STAGE_NAMES, np.round(stage_ms, 4).tolist())),
                                              "stage_cells": dict(zip(X.STAGE_NAMES, [int(v) for v in stage_cells])),
@@ -266,38 +333,57 @@ def main():
         print(json.dumps(out))
         return
 
-    # plain form: the same records as sequential 10,000-record batches
+    # plain form: the same records as sequential 10,000-record launches
+    # ("Method", Baseline), over --plain-steps passes of the whole batch
     pctx = X.Context(wl.store, mode=X.MODE_PLAIN)
     pctx.set_tuning(**tuning)
-    chunk = 10000
-    plat = []
-    for _ in range(1):  # warm-up
-        pctx.wait(pctx.submit_device(d_recs[: chunk * 32], min(chunk, n), d_out, None, stream=stream))
-    torch.cuda.synchronize()
-    p_start = time.perf_counter()
-    for _ in range(args.plain_steps):
-        for off in range(0, n, chunk):
-            m = min(chunk, n - off)
-            s0 = time.perf_counter()
-            pctx.wait(pctx.submit_device(d_recs[off * 32:(off + m) * 32], m, d_out[off * 32:(off + m) * 32], None,
-                                         stream=stream))
-            plat.append((time.perf_counter() - s0) * 1e3)
-    torch.cuda.synchronize()
-    p_elapsed = time.perf_counter() - p_start
-    plain_gcups = total_cells * args.plain_steps / p_elapsed / 1e9
+    chunked(pctx, 1)   # warm-up
+    p_el, plat, ppass = chunked(pctx, args.plain_steps)
+    plain_gcups = total_cells * args.plain_steps / p_el / 1e9
     res_p = d_out.cpu().numpy().view(W.RESULT_DTYPE)
     pctx.close()
-    out["plain"] = {"gcups": round(plain_gcups, 2), "p50_ms": pct(plat, 50), "p99_ms": pct(plat, 99),
-                    "batch_records": chunk, "ms_per_pass": round(p_elapsed * 1e3 / args.plain_steps, 3),
-                    "alignments_per_s": round(n * args.plain_steps / p_elapsed, 1),
+    out["plain"] = {"gcups": round(plain_gcups, 2), "alignments_per_s": round(n * args.plain_steps / p_el, 1),
+                    "requests_10k": {"p50_ms": pct(plat, 50), "p99_ms": pct(plat, 99), "batch_records": chunk,
+                                     "batches": len(plat)},
+                    "whole_batch": {"p50_ms": pct(ppass, 50), "p99_ms": pct(ppass, 99), "batch_records": n,
+                                    "passes": args.plain_steps},
                     "results_equal_batched": bool(np.array_equal(res_p, res_gpu))}
-    out["batched_over_plain"] = round(gcups / plain_gcups, 3)
-    log(f"plain: {plain_gcups:.1f} GCUPS, p50 {out['plain']['p50_ms']:.2f} ms per 10k batch")
+    out["batched_over_plain"] = {
+        "gcups": round(gcups / plain_gcups, 3),
+        "p99_whole_batch": round(out["plain"]["whole_batch"]["p99_ms"] / pct(lat, 99), 3),
+        "p99_requests_10k": round(plat and small and pct(plat, 99) / small["p99_ms"] or 0.0, 3)}
+    log(f"plain: {plain_gcups:.1f} GCUPS; 10k requests p50 {pct(plat, 50):.2f} ms p99 {pct(plat, 99):.2f} ms; "
+        f"whole batch p50 {pct(ppass, 50):.1f} ms p99 {pct(ppass, 99):.1f} ms")
+
+    if not args.no_side_c1 and args.workload != "c1" and args.pairs is None:
+        # side line: the 29x-shaped batch (c1) with the same launch parameters
+        w1 = W.make_workload("c1")
+        n1 = len(w1.records)
+        r1 = torch.from_numpy(w1.records.view(np.uint8).copy()).to(dev)
+        o1 = torch.zeros(n1 * 32, dtype=torch.uint8, device=dev)
+        c1cells = torch.zeros(n1, dtype=torch.int64, device=dev)
+        with X.Context(w1.store, mode=X.MODE_PERSISTENT) as cx:
+            cx.set_tuning(**tuning)
+            cx.wait(cx.submit_device(r1, n1, o1, c1cells, stream=stream))
+            torch.cuda.synchronize()
+            cells1 = int(c1cells.sum().item())
+            for _ in range(2):
+                cx.wait(cx.submit_device(r1, n1, o1, None, stream=stream))
+            torch.cuda.synchronize()
+            k1 = max(5, args.steps // 2)
+            t1 = time.perf_counter()
+            for _ in range(k1):
+                cx.wait(cx.submit_device(r1, n1, o1, None, stream=stream))
+            torch.cuda.synchronize()
+            el1 = time.perf_counter() - t1
+        out["c1"] = {"workload": f"c1: {n1:,} {WORKLOAD_TEXT['c1']}", "gcups": round(cells1 * k1 / el1 / 1e9, 2),
+                     "ms_per_batch": round(el1 * 1e3 / k1, 3), "cells": cells1, "steps": k1}
+        log(f"c1 side line: {out['c1']['ms_per_batch']:.2f} ms per batch, {out['c1']['gcups']:.1f} GCUPS")
 
     if not args.no_cpu_baseline:
         import oracle
         S = min(args.cpu_sample, n)
-        threads = min(os.cpu_count() or 1, 16)
+        threads = oracle.default_threads()
         c0 = time.perf_counter()
         ref, used = oracle.batch(wl.store.codes, wl.store.off, wl.store.length, recs[:S], nthreads=threads)
         c_el = time.perf_counter() - c0
@@ -308,11 +394,14 @@ def main():
                        ("b_begin", "b_begin"), ("b_end", "b_end")):
             same &= res_gpu[fg][:S].astype(np.int64) == ref[fr].astype(np.int64)
         same &= cells_rec[:S] == (ref["cells_left"] + ref["cells_right"]).astype(np.uint64)
+        host = host_cpu()
         out["cpu_baseline"] = {"value": round(ref_cells / c_el / 1e9, 3), "unit": "GCUPS", "cores": int(used),
                                "kind": "oracle",
-                               "sample": f"first {S} records of {args.workload} ({ref_cells} cells, {c_el:.1f} s)"}
+                               "sample": f"first {S} records of {args.workload} ({ref_cells} cells, {c_el:.1f} s "
+                                         f"on {used} threads)",
+                               "host": {**host, "threads_rule": "min(CPUs allowed, 16): the host share of one GPU"}}
         out["parity_sample"] = f"{int(same.sum())}/{S} records bit-exact (results and cells) vs oracle"
-        log(f"cpu oracle: {ref_cells / c_el / 1e9:.3f} GCUPS on {used} threads; parity {int(same.sum())}/{S}")
+        log(f"cpu oracle: {ref_cells / c_el / 1e9:.3f} GCUPS on {used} threads ({host}); parity {int(same.sum())}/{S}")
         # the same oracle on one host thread, over a tenth of the sample
         S1 = max(1, S // 10)
         c0 = time.perf_counter()
@@ -422,29 +511,46 @@ def serve_main(args):
     P = args.producers
 
     def batch_at(r):
-        z = int(r.integers(1000, 50001))
-        s0 = int(r.integers(0, len(recs) - z))
+        # batch size U[1000, 50000], clamped to the pool; start anywhere it fits
+        z = min(int(r.integers(1000, 50001)), len(recs))
+        s0 = int(r.integers(0, len(recs) - z + 1))
         return s0, z
 
-    def run_phase(rate, seconds, closed, gran=0):
+    def run_phase(rate, seconds, closed, gran=0, min_batches=0):
+        """One load point: open loop at `rate` batches/s (closed: back to back)
+        for `seconds`, extended until `min_batches` batches have completed."""
         lat, done_recs, done_cells = [], [0], [0]
         lock = threading.Lock()
         t_begin = time.perf_counter()
 
+        errors = []
+
         def producer(p):
+            try:
+                produce(p)
+            except BaseException as e:   # re-raised in the caller after join
+                errors.append(e)
+
+        def produce(p):
             r = np.random.default_rng(1000 + p)
             t_next = t_begin
+            def over(t):
+                if t - t_begin <= seconds:
+                    return False
+                with lock:
+                    return len(lat) >= min_batches
+
             while True:
                 if not closed:
                     t_next += r.exponential(P / rate)
-                    if t_next - t_begin > seconds:
+                    if over(t_next):
                         break
                     now = time.perf_counter()
                     if t_next > now:
                         time.sleep(t_next - now)
                 else:
                     t_next = time.perf_counter()
-                    if t_next - t_begin > seconds:
+                    if over(t_next):
                         break
                 s0, z = batch_at(r)
                 if gran <= 0 or z <= gran:
@@ -462,8 +568,16 @@ def serve_main(args):
         th = [threading.Thread(target=producer, args=(p,)) for p in range(P)]
         for t in th:
             t.start()
+        last = time.perf_counter()
         for t in th:
-            t.join()
+            while t.is_alive():
+                t.join(timeout=5.0)
+                if time.perf_counter() - last > 30.0:   # a long point reports how far it got
+                    last = time.perf_counter()
+                    with lock:
+                        log(f"  ... {len(lat)} batches after {last - t_begin:.0f} s")
+        if errors:
+            raise errors[0]
         el = time.perf_counter() - t_begin
         return {"offered_batches_per_s": None if closed else rate, "batches": len(lat),
                 "achieved_batches_per_s": len(lat) / el, "alignments_per_s": done_recs[0] / el,
@@ -476,7 +590,7 @@ def serve_main(args):
         points = []
         for f in [float(x) for x in args.serve_points.split(",")]:
             rate = f * sat["achieved_batches_per_s"]
-            r = run_phase(rate, args.serve_seconds, False, gran)
+            r = run_phase(rate, args.serve_seconds, False, gran, args.serve_min_batches)
             r["load_fraction"] = f
             points.append(r)
             log(f"sub-batch {gran}, load {f:.1f}: {r['achieved_batches_per_s']:.1f} b/s, "

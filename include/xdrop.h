@@ -194,10 +194,13 @@ xdrop_status xdrop_get_tuning(const xdrop_ctx *c, xdrop_tuning *out);
  * (XDROP_E_BUSY otherwise).  Values are clamped to their valid ranges. */
 xdrop_status xdrop_set_tuning(xdrop_ctx *c, const xdrop_tuning *t);
 
-/* Autotuner: run the n host records (a representative sample, e.g. 10k-50k
- * records) under a grid of launch parameters -- persistent grid size, length
- * bucketing, adaptive window margins -- keep the fastest by device time and
- * make it the context's tuning.  When cache_path is non-NULL the choice is
+/* Autotuner: run the n host records (a representative sample, e.g. 10k-200k
+ * records) under launch parameters chosen by coordinate descent -- each knob
+ * (persistent grid size, length bucketing, adaptive window margins, grid of
+ * the unbounded-band kernel) swept in turn with the others at the best so
+ * far, two rounds, each setting timed by the better of two runs after a
+ * warm-up -- keep the fastest by device time and make it the context's
+ * tuning.  Every setting gives the same results.  When cache_path is non-NULL the choice is
  * written there (text, one "key value" per line) and later contexts created
  * with cfg->tuning_cache = cache_path start from it.  *best_ms (nullable)
  * gets the best device time.  Only while no batch is in flight. */
@@ -260,7 +263,9 @@ xdrop_status xdrop_find_seeds(xdrop_ctx *c, const xdrop_seed_params *p, xdrop_re
 /* Human-readable text of a status code (static storage). */
 const char *xdrop_status_string(xdrop_status s);
 
-/* Last error message recorded on the context (or globally when c is NULL). */
+/* Last error message recorded on the context (or globally when c is NULL).
+ * The text is a copy owned by the calling thread, valid until that thread
+ * calls xdrop_last_error again; safe while other threads record errors. */
 const char *xdrop_last_error(const xdrop_ctx *c);
 
 #ifdef __cplusplus

@@ -148,11 +148,18 @@ struct xdrop_ctx {
     uint64_t next_id = 1;
     bool stop = false;
     bool poisoned = false;
+
+    // last error text: its own lock, since fail() is called both with and
+    // without mu held (slot workers, submit, find_seeds)
+    mutable std::mutex err_mu;
     std::string err;
 
     void fail(const std::string &s)
     {
-        err = s;
+        {
+            std::lock_guard<std::mutex> lk(err_mu);
+            err = s;
+        }
         set_global_error(s);
     }
 };
@@ -250,6 +257,8 @@ size_t slot_bytes(uint32_t cap)
     return b;
 }
 
+// Releases every buffer of a slot and leaves it empty (cap 0, no pointers):
+// an empty slot is never picked for a batch.
 void free_slot_buffers(Slot &s)
 {
     for (auto &g : s.graph)
@@ -266,6 +275,10 @@ void free_slot_buffers(Slot &s)
     s.h_stage = nullptr;
     s.dblock = nullptr; s.scratch = nullptr; s.h_recs = nullptr; s.h_res = nullptr; s.h_cells = nullptr;
     s.h_misc = nullptr;
+    s.dev = BatchDev{};
+    s.d_n = nullptr;
+    s.scratch_stride = 0;
+    s.generic_blocks = 0;
     s.cap = 0;
     s.bytes = 0;
 }
@@ -283,11 +296,30 @@ uint32_t slot_generic_blocks(const xdrop_ctx *c)
     return (uint32_t)std::min<uint64_t>(generic_blocks(c->tune.generic_waves), fit);
 }
 
+// Allocates the buffers of an empty slot for `cap` records.  All or nothing:
+// on failure everything allocated here is released, the slot stays empty
+// (cap 0) and the error is rethrown.
+void alloc_slot_buffers_impl(xdrop_ctx *c, Slot &s, uint32_t cap);
+
 void alloc_slot_buffers(xdrop_ctx *c, Slot &s, uint32_t cap)
 {
-    s.cap = cap;
-    s.bytes = slot_bytes(cap);
-    HIP_TRY(hipMalloc(&s.dblock, s.bytes));
+    try {
+        alloc_slot_buffers_impl(c, s, cap);
+    } catch (...) {
+        (void)hipGetLastError();   // an allocation failure must not linger as the stream's error
+        free_slot_buffers(s);
+        throw;
+    }
+}
+
+void alloc_slot_buffers_impl(xdrop_ctx *c, Slot &s, uint32_t cap)
+{
+    // pointers are committed to the slot as they are allocated (so that a
+    // failure can release them); cap and bytes only once everything exists
+    s.cap = 0;
+    s.bytes = 0;
+    const size_t dbytes = slot_bytes(cap);
+    HIP_TRY(hipMalloc(&s.dblock, dbytes));
     char *p = (char *)s.dblock;
     auto take = [&](size_t x) {
         char *q = p;
@@ -314,8 +346,8 @@ void alloc_slot_buffers(xdrop_ctx *c, Slot &s, uint32_t cap)
     // unbounded-kernel scratch: three anti-diagonals per workgroup
     s.generic_blocks = slot_generic_blocks(c);
     s.scratch_stride = scratch_stride_of(c);
-    HIP_TRY(hipMalloc(&s.scratch, (size_t)s.generic_blocks * 3 * s.scratch_stride * sizeof(int32_t)));
-    s.bytes += (size_t)s.generic_blocks * 3 * s.scratch_stride * sizeof(int32_t);
+    const size_t sbytes = (size_t)s.generic_blocks * 3 * s.scratch_stride * sizeof(int32_t);
+    HIP_TRY(hipMalloc(&s.scratch, sbytes));
     HIP_TRY(hipHostMalloc((void **)&s.h_recs, n * sizeof(xdrop_record), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void **)&s.h_res, n * sizeof(xdrop_result), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void **)&s.h_cells, n * sizeof(uint64_t), hipHostMallocDefault));
@@ -327,6 +359,8 @@ void alloc_slot_buffers(xdrop_ctx *c, Slot &s, uint32_t cap)
         s.sev.resize((kNumStages + 1) * sets, nullptr);
         for (auto &e : s.sev) HIP_TRY(hipEventCreate(&e));
     }
+    s.cap = cap;
+    s.bytes = dbytes + sbytes;
 }
 
 size_t slot_footprint(const xdrop_ctx *c, uint32_t cap)
@@ -341,31 +375,41 @@ uint32_t round_cap(size_t n)
     return c;
 }
 
+// Scratch of the unbounded-band kernel: `blocks` workgroups, three
+// anti-diagonals of `stride` ints each.
+struct GenericScratch {
+    int32_t *base;
+    uint64_t stride;
+    uint32_t blocks;
+};
+
 // Kernel sequence of one batch (or chunk) on `s`.  `b` may be a view into the
 // slot buffers (plain chunks); n_src non-null means "read n from device".
-void enqueue_kernels(xdrop_ctx *c, Slot &sl, const BatchDev &b, uint32_t n, const uint32_t *n_src, bool persistent,
-                     bool count, hipStream_t s, hipEvent_t *ev)
+void enqueue_kernels(xdrop_ctx *c, const Tuning &tu, const GenericScratch &gs, const BatchDev &b, uint32_t n,
+                     const uint32_t *n_src, bool persistent, bool count, hipStream_t s, hipEvent_t *ev)
 {
     // ev (nullable): kNumStages + 1 stage-boundary events recorded between the launches
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     launch_reset_n(b, n_src, n, s);
-    const bool stage = persistent && c->tune.buckets > 0;
-    launch_prep(b, c->st, c->tune, n, stage, s);
+    const bool stage = persistent && tu.buckets > 0;
+    launch_prep(b, c->st, tu, n, stage, s);
     if (stage) launch_bucket(b, c->st, n, s);
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
-    const uint32_t resident = (uint32_t)c->cus * (uint32_t)std::max(1, c->tune.waves_per_cu);
+    const uint32_t resident = (uint32_t)c->cus * (uint32_t)std::max(1, tu.waves_per_cu);
     // plain form: one wavefront per extension for the first class
-    launch_adaptive(b, c->st, c->tune, persistent ? resident : std::max<uint32_t>(2 * n, 4), count, s);
+    launch_adaptive(b, c->st, tu, persistent ? resident : std::max<uint32_t>(2 * n, 4), count, s);
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
     for (int w = 0; w < kWideClasses; ++w) {
         launch_wide(w, b, c->st, (uint32_t)c->cus * 8u, count, s);
         if (ev) HIP_TRY(hipEventRecord(ev[3 + w], s));
     }
-    launch_generic(b, c->st, sl.scratch, sl.scratch_stride, sl.generic_blocks, count, s);
+    launch_generic(b, c->st, gs.base, gs.stride, gs.blocks, count, s);
     if (ev) HIP_TRY(hipEventRecord(ev[2 + kNumClasses - 1], s));
     launch_finalize(b, c->st, n, count, s);
     if (ev) HIP_TRY(hipEventRecord(ev[kNumStages], s));
 }
+
+GenericScratch slot_scratch(const Slot &sl) { return GenericScratch{sl.scratch, sl.scratch_stride, sl.generic_blocks}; }
 
 // The persistent form's kernel sequence captured once per slot (and per cell
 // counting flag); kernels read the batch size from device memory, so one
@@ -380,7 +424,7 @@ hipGraphExec_t get_graph(xdrop_ctx *c, Slot &sl, bool count)
     (void)hipGetLastError();   // start the capture with no stale error
     HIP_TRY(hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal));
     try {
-        enqueue_kernels(c, sl, sl.dev, sl.cap, sl.d_n, true, count, sl.stream, nullptr);
+        enqueue_kernels(c, c->tune, slot_scratch(sl), sl.dev, sl.cap, sl.d_n, true, count, sl.stream, nullptr);
     } catch (...) {
         hipStreamEndCapture(sl.stream, &graph);
         if (graph) hipGraphDestroy(graph);
@@ -417,14 +461,14 @@ void run_batch(xdrop_ctx *c, Slot &sl, Ticket &t)
         if (!c->profile)
             HIP_TRY(hipGraphLaunch(get_graph(c, sl, count), s));
         else
-            enqueue_kernels(c, sl, sl.dev, n, nullptr, true, count, s, sl.sev.data());
+            enqueue_kernels(c, c->tune, slot_scratch(sl), sl.dev, n, nullptr, true, count, s, sl.sev.data());
     } else {
         HIP_TRY(hipMemsetAsync(sl.d_n + 1, 0, sizeof(uint32_t), s));
         for (uint32_t off = 0; off < n; off += kPlainChunk) {
             const uint32_t m = std::min(kPlainChunk, n - off);
             BatchDev v = sl.dev;
             v.recs += off; v.res += off; v.cells += off; v.seed += off; v.valid += off; v.tout += 2 * (size_t)off;
-            enqueue_kernels(c, sl, v, m, nullptr, false, count, s,
+            enqueue_kernels(c, c->tune, slot_scratch(sl), v, m, nullptr, false, count, s,
                             c->profile ? sl.sev.data() + (kNumStages + 1) * (size_t)(off / kPlainChunk) : nullptr);
             // chunk errors accumulate in the slot's error word
             launch_accum_errors(v, sl.d_n + 1, s);
@@ -534,7 +578,10 @@ Slot *new_slot(xdrop_ctx *c)
 }
 
 // Admission (called with c->mu held): a free slot with enough capacity, or a
-// new / re-sized slot when the HBM budget allows.  Returns nullptr if none.
+// new / re-sized slot when the HBM budget allows.  Returns nullptr if none;
+// then at least one slot is busy (a batch that fits the budget alone always
+// fits once every idle slot has been emptied), and its completion wakes the
+// waiters.  Throws when an allocation fails (the slot involved is left empty).
 Slot *try_admit(xdrop_ctx *c, size_t n)
 {
     Slot *best = nullptr;
@@ -550,18 +597,30 @@ Slot *try_admit(xdrop_ctx *c, size_t n)
         c->used += s->bytes;
         return s;
     }
-    // re-size the largest idle slot
-    Slot *idle = nullptr;
+    // re-size idle slots: empty them, largest first, until the batch fits;
+    // nothing is released unless that makes room
+    std::vector<Slot *> idle;
+    size_t idle_bytes = 0;
     for (auto &s : c->slots)
-        if (!s->busy && (!idle || s->cap > idle->cap)) idle = s.get();
-    if (idle && c->used - idle->bytes + need <= c->budget) {
-        c->used -= idle->bytes;
-        free_slot_buffers(*idle);
-        alloc_slot_buffers(c, *idle, cap);
-        c->used += idle->bytes;
-        return idle;
+        if (!s->busy) {
+            idle.push_back(s.get());
+            idle_bytes += s->bytes;
+        }
+    if (idle.empty() || c->used - idle_bytes + need > c->budget) return nullptr;
+    std::sort(idle.begin(), idle.end(), [](const Slot *a, const Slot *b) { return a->bytes > b->bytes; });
+    Slot *target = idle[0];
+    for (Slot *s : idle) {
+        if (c->used + need <= c->budget) break;
+        c->used -= s->bytes;
+        free_slot_buffers(*s);
     }
-    return nullptr;
+    if (target->cap) {   // the largest idle slot was not needed for room: empty it too, it is re-sized
+        c->used -= target->bytes;
+        free_slot_buffers(*target);
+    }
+    alloc_slot_buffers(c, *target, cap);
+    c->used += target->bytes;
+    return target;
 }
 
 xdrop_status submit_common(xdrop_ctx *c, std::shared_ptr<Ticket> t, const xdrop_record *host_recs,
@@ -597,7 +656,12 @@ xdrop_status submit_common(xdrop_ctx *c, std::shared_ptr<Ticket> t, const xdrop_
         if (admit_timeout_us < 0) {
             c->cv.wait(lk);
         } else if (c->cv.wait_until(lk, deadline) == std::cv_status::timeout) {
-            sl = try_admit(c, t->n);
+            try {
+                sl = try_admit(c, t->n);
+            } catch (const std::exception &e) {
+                c->fail(e.what());
+                return XDROP_E_NOMEM;
+            }
             if (!sl) return XDROP_E_BUSY;
             break;
         }
@@ -685,9 +749,16 @@ const char *xdrop_status_string(xdrop_status s)
 
 const char *xdrop_last_error(const xdrop_ctx *c)
 {
-    if (c) return c->err.c_str();
-    std::lock_guard<std::mutex> lk(g_err_mu);
-    return g_err_text.c_str();
+    // a copy per calling thread: valid until that thread's next call
+    thread_local std::string copy;
+    if (c) {
+        std::lock_guard<std::mutex> lk(c->err_mu);
+        copy = c->err;
+    } else {
+        std::lock_guard<std::mutex> lk(g_err_mu);
+        copy = g_err_text;
+    }
+    return copy.c_str();
 }
 
 xdrop_status xdrop_batch_create(const xdrop_config *cfg, xdrop_ctx **out)
@@ -910,23 +981,10 @@ xdrop_status xdrop_autotune(xdrop_ctx *c, const xdrop_record *recs, size_t n, co
         ms = s.device_ms;
         return st;
     };
-    std::vector<Tuning> grid;
-    const int wpc[] = {8, 16, 24, 32};
-    const int margins[][2] = {{2, 2}, {4, 2}, {6, 3}, {8, 4}, {8, 6}, {12, 8}, {16, 12}};
-    for (int w : wpc)
-        for (int b = 0; b <= 1; ++b)
-            for (auto &mg : margins) {
-                Tuning t = c->tune;
-                t.waves_per_cu = w;
-                t.buckets = b;
-                t.grow_margin = mg[0];
-                t.shrink_margin = mg[1];
-                grid.push_back(t);
-            }
-    const Tuning start = c->tune;
-    Tuning best = start;
-    double best_t = 1e300;
-    for (const Tuning &cand : grid) {
+    // Coordinate descent: each knob in turn is swept over its values with the
+    // others held at the best setting so far; two rounds.  A setting is timed
+    // by the better of two runs after a warm-up run (graph capture).
+    auto measure = [&](const Tuning &cand, double &ms) -> xdrop_status {
         {
             std::lock_guard<std::mutex> lk(c->mu);
             try {
@@ -937,14 +995,46 @@ xdrop_status xdrop_autotune(xdrop_ctx *c, const xdrop_record *recs, size_t n, co
             }
         }
         double ms0 = 0, ms1 = 0, ms2 = 0;
-        xdrop_status st = time_once(ms0);           // graph capture and warm-up
+        xdrop_status st = time_once(ms0);
         if (st == XDROP_OK) st = time_once(ms1);
         if (st == XDROP_OK) st = time_once(ms2);
+        ms = std::min(ms1, ms2);
+        return st;
+    };
+    struct Knob {
+        std::vector<std::pair<int, int>> values;   // (first, second) field values
+        void (*set)(Tuning &, std::pair<int, int>);
+    };
+    const std::vector<Knob> knobs = {
+        {{{8, 0}, {16, 0}, {24, 0}, {32, 0}, {40, 0}}, [](Tuning &t, std::pair<int, int> v) { t.waves_per_cu = v.first; }},
+        {{{0, 0}, {1, 0}}, [](Tuning &t, std::pair<int, int> v) { t.buckets = v.first; }},
+        {{{2, 2}, {4, 2}, {6, 3}, {8, 4}, {8, 6}, {12, 8}, {16, 12}},
+         [](Tuning &t, std::pair<int, int> v) { t.grow_margin = v.first; t.shrink_margin = v.second; }},
+        {{{256, 0}, {1024, 0}, {4096, 0}},
+         [](Tuning &t, std::pair<int, int> v) { t.generic_waves = v.first; }},
+    };
+    const Tuning start = c->tune;
+    Tuning best = start;
+    double best_t = 1e300;
+    {
+        const xdrop_status st = measure(best, best_t);
         if (st != XDROP_OK) return st;
-        const double ms = std::min(ms1, ms2);
-        if (ms < best_t) {
-            best_t = ms;
-            best = cand;
+    }
+    for (int round = 0; round < 2; ++round) {
+        for (const Knob &k : knobs) {
+            for (const auto &v : k.values) {
+                Tuning cand = best;
+                k.set(cand, v);
+                clamp_tuning(cand);
+                if (std::memcmp(&cand, &best, sizeof(Tuning)) == 0) continue;
+                double ms = 0;
+                const xdrop_status st = measure(cand, ms);
+                if (st != XDROP_OK) return st;
+                if (ms < best_t) {
+                    best_t = ms;
+                    best = cand;
+                }
+            }
         }
     }
     {
