@@ -55,9 +55,13 @@ assert REC_DTYPE.itemsize == ctypes.sizeof(Rec)
 def build(out_path: str = _LIB_PATH, mutation: int = 0) -> str:
     """Compile the oracle with gcc.  ``mutation`` > 0 plants a known mistake
     (used only by the tests that show the pins catch mistakes)."""
+    # built beside the target and renamed over it, so that a process that has
+    # the old library loaded keeps a valid mapping
+    tmp = f"{out_path}.tmp{os.getpid()}"
     cmd = ["gcc", "-O2", "-shared", "-fPIC", "-pthread", f"-DOX_MUTATION={int(mutation)}",
-           _SRC, "-o", out_path]
+           _SRC, "-o", tmp]
     subprocess.run(cmd, check=True)
+    os.replace(tmp, out_path)
     return out_path
 
 
@@ -69,6 +73,8 @@ def _bind(lib):
         f = getattr(lib, name)
         f.argtypes = [u8p, i64, u8p, i64, i64, i64, i64, i64, P(Ext)]
         f.restype = ctypes.c_int
+    lib.ox_extend_band.argtypes = [u8p, i64, u8p, i64, i64, i64, i64, i64, P(Ext), i64p]
+    lib.ox_extend_band.restype = ctypes.c_int
     lib.ox_nw_best.argtypes = [u8p, i64, u8p, i64, i64, i64, i64, P(Ext)]
     lib.ox_nw_best.restype = ctypes.c_int
     lib.ox_record.argtypes = [u8p, i64, u8p, i64, i64, i64, i64, ctypes.c_int, i64, i64, i64, i64,
@@ -132,6 +138,20 @@ def extend(a, b, ma=1, mi=-1, g=-1, X=50, dense=False, lib=None):
     return out.tup()
 
 
+def extend_band(a, b, ma=1, mi=-1, g=-1, X=50, lib=None):
+    """extend() plus the widest live range of any anti-diagonal:
+    ((T, i*, j*, cells), max_width)."""
+    lib = lib or load()
+    a, b = codes(a), codes(b)
+    pa, ka = _u8(a)
+    pb, kb = _u8(b)
+    out = Ext()
+    w = ctypes.c_int64()
+    if lib.ox_extend_band(pa, a.size, pb, b.size, ma, mi, g, X, ctypes.byref(out), ctypes.byref(w)) != 0:
+        raise MemoryError("oracle extend failed")
+    return out.tup(), int(w.value)
+
+
 def nw_best(a, b, ma=1, mi=-1, g=-1, lib=None):
     """Full Needleman-Wunsch prefix table maximum: (H*, i*, j*, (m+1)(n+1)-1)."""
     lib = lib or load()
@@ -160,6 +180,16 @@ def record(A, B, pos_a, pos_b, k, strand, X, ma=1, mi=-1, g=-1, lib=None) -> dic
     return {name: getattr(out, name) for name, _ in Rec._fields_}
 
 
+def default_threads() -> int:
+    """Host threads for batch(): the CPUs this process may run on, at most
+    16 (the host share of one GPU on a shared multi-GPU node)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
 def batch(read_codes: np.ndarray, read_off: np.ndarray, read_len: np.ndarray, recs,
           nthreads: int | None = None, lib=None):
     """Run ``ox_record`` over a record table on a pool of threads.
@@ -172,7 +202,7 @@ def batch(read_codes: np.ndarray, read_off: np.ndarray, read_len: np.ndarray, re
     lib = lib or load()
     n = len(recs["read_a"])
     if nthreads is None:
-        nthreads = os.cpu_count() or 1
+        nthreads = default_threads()
     cols = [np.ascontiguousarray(recs[f], dtype=np.int64) for f in
             ("read_a", "read_b", "pos_a", "pos_b", "k", "strand", "x", "match", "mismatch", "gap")]
     codes_arr = np.ascontiguousarray(read_codes, dtype=np.uint8)

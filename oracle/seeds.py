@@ -34,7 +34,18 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["kmer_occurrences", "reliable_kmers", "find_seeds"]
+__all__ = ["kmer_occurrences", "reliable_kmers", "find_seeds", "SEED_RECORD_DTYPE"]
+
+# Layout of one output record: the 32-byte seed-and-extend record of the
+# library's C ABI (read ids, seed start in both reads' stored coordinates,
+# seed length, strand, drop and weights), restated here so that this module
+# depends on nothing outside oracle/.
+SEED_RECORD_DTYPE = np.dtype([
+    ("read_a", "<u4"), ("read_b", "<u4"), ("pos_a", "<u4"), ("pos_b", "<u4"),
+    ("k", "<u2"), ("strand", "u1"), ("pad", "u1"), ("x", "<i4"),
+    ("match", "<i2"), ("mismatch", "<i2"), ("gap", "<i2"), ("pad2", "<i2"),
+])
+assert SEED_RECORD_DTYPE.itemsize == 32
 
 
 def kmer_occurrences(codes: np.ndarray, off: np.ndarray, length: np.ndarray, k: int, stride: int = 1):
@@ -72,9 +83,7 @@ def reliable_kmers(keys: np.ndarray, lo: int, hi: int) -> np.ndarray:
 
 def find_seeds(codes, off, length, k: int = 31, stride: int = 1, lo: int = 20, hi: int = 30,
                x: int = 15, weights=(1, -1, -1)) -> np.ndarray:
-    """Steps 1-6: seed records (RECORD_DTYPE layout) ordered by (read_a, read_b)."""
-    from paper_2309_07270_amd.workload import RECORD_DTYPE   # the record layout only
-
+    """Steps 1-6: seed records (SEED_RECORD_DTYPE) ordered by (read_a, read_b)."""
     keys, reads, poss, revs = kmer_occurrences(codes, off, length, k, stride)
     rel = reliable_kmers(keys, lo, hi)
     sel = np.isin(keys, rel)
@@ -95,7 +104,7 @@ def find_seeds(codes, off, length, k: int = 31, stride: int = 1, lo: int = 20, h
                 pair = (int(reads[a]), int(reads[b]))
                 if pair not in best or cand < best[pair]:
                     best[pair] = cand
-    out = np.zeros(len(best), RECORD_DTYPE)
+    out = np.zeros(len(best), SEED_RECORD_DTYPE)
     for t, (pair, (pa, pb, st)) in enumerate(sorted(best.items())):
         out[t]["read_a"], out[t]["read_b"] = pair
         out[t]["pos_a"], out[t]["pos_b"], out[t]["strand"] = pa, pb, st

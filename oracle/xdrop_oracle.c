@@ -86,9 +86,14 @@ static int64_t ox_sigma(uint8_t x, uint8_t y, int64_t ma, int64_t mi)
 /* any lookup outside that range reads as "not live".  Only cells that can   */
 /* have a live predecessor are visited.                                      */
 /* ------------------------------------------------------------------------ */
-int ox_extend(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
-              int64_t ma, int64_t mi, int64_t g, int64_t X, ox_ext_t *out)
+/* max_width (nullable): the widest live range hi - lo + 1 over all
+   anti-diagonals, written when non-NULL (an observation of the run; it
+   changes nothing in it). */
+static int ox_extend_core(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
+                          int64_t ma, int64_t mi, int64_t g, int64_t X, ox_ext_t *out,
+                          int64_t *max_width)
 {
+    if (max_width) *max_width = 1;   /* anti-diagonal 0: (0,0) */
     int64_t *buf[3];
     for (int t = 0; t < 3; ++t) {
         buf[t] = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m + 2));
@@ -151,6 +156,7 @@ int ox_extend(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
 #endif
         }
         const int live = nlo <= nhi;
+        if (max_width && live && nhi - nlo + 1 > *max_width) *max_width = nhi - nlo + 1;
 #if OX_MUTATION == 7
         if (live && dmax >= T) { T = dmax; bi = dmi; bj = d - dmi; } /* planted: later diagonal wins ties */
 #else
@@ -168,6 +174,21 @@ int ox_extend(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
     out->score = T; out->i = bi; out->j = bj; out->cells = cells;
     for (int u = 0; u < 3; ++u) free(buf[u]);
     return 0;
+}
+
+int ox_extend(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
+              int64_t ma, int64_t mi, int64_t g, int64_t X, ox_ext_t *out)
+{
+    return ox_extend_core(a, m, b, n, ma, mi, g, X, out, NULL);
+}
+
+/* The same extension, also reporting the widest live range of an
+   anti-diagonal (used by tests to predict which band widths a run meets). */
+int ox_extend_band(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
+                   int64_t ma, int64_t mi, int64_t g, int64_t X, ox_ext_t *out,
+                   int64_t *max_width)
+{
+    return ox_extend_core(a, m, b, n, ma, mi, g, X, out, max_width);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -1,6 +1,10 @@
 """Pins of the CPU oracle against things other than itself.
 
 * hand-traced extensions (tests/golden/hand_traces.txt);
+* worked extensions and a worked record from an implementation of the
+  reading written independently of the oracle, including vectors on which
+  other readings of X-drop differ and the non-monotone-in-X example
+  (tests/golden/reading_vectors.txt, tests/golden/worked_record.txt);
 * brute force: with a drop so large that nothing is ever pruned, the X-drop
   result must be the best cell of the full Needleman-Wunsch prefix table with
   the tie-break (max score, min i+j, min i); that table is itself checked
@@ -48,6 +52,37 @@ def read_golden():
     return rows
 
 
+VECTORS = os.path.join(os.path.dirname(__file__), "golden", "reading_vectors.txt")
+RECORD = os.path.join(os.path.dirname(__file__), "golden", "worked_record.txt")
+
+
+def read_vectors():
+    """(a, b, ma, mi, g, X, (T, i, j, cells or None)) rows of reading_vectors.txt."""
+    rows = []
+    for line in open(VECTORS):
+        line = line.split("#")[0].strip()
+        if not line:
+            continue
+        lhs, rhs = line.split("->")
+        a, b, ma, mi, g, X = lhs.split()
+        T, i, j, cells = rhs.split()
+        rows.append(("" if a == "-" else a, "" if b == "-" else b, int(ma), int(mi), int(g), int(X),
+                     (int(T), int(i), int(j), None if cells == "*" else int(cells))))
+    return rows
+
+
+def read_records():
+    rows = []
+    for line in open(RECORD):
+        line = line.split("#")[0].strip()
+        if not line:
+            continue
+        lhs, rhs = line.split("->")
+        A, B, *nums = lhs.split()
+        rows.append((A, B, [int(v) for v in nums], [int(v) for v in rhs.split()]))
+    return rows
+
+
 def rand_seq(rng, lo, hi):
     return "".join(rng.choice(list(ALPHA), int(rng.integers(lo, hi + 1))))
 
@@ -72,6 +107,26 @@ def pin_hand_traces(lib):
         got = oracle.extend(a, b, ma, mi, g, X, lib=lib)
         if got != want:
             bad.append((a, b, X, got, want))
+    return bad
+
+
+def pin_reading_vectors(lib):
+    bad = []
+    for a, b, ma, mi, g, X, want in read_vectors():
+        got = oracle.extend(a, b, ma, mi, g, X, lib=lib)
+        if got[:3] != want[:3] or (want[3] is not None and got[3] != want[3]):
+            bad.append((a, b, X, got, want))
+    return bad
+
+
+def pin_worked_record(lib):
+    keys = ("score", "left", "right", "seed", "a_begin", "a_end", "b_begin", "b_end", "cells_left", "cells_right")
+    bad = []
+    for A, B, (pa, pb, k, strand, X, ma, mi, g), want in read_records():
+        r = oracle.record(A, B, pa, pb, k, strand, X, ma, mi, g, lib=lib)
+        got = [r[key] for key in keys]
+        if got != want:
+            bad.append((A, B, strand, got, want))
     return bad
 
 
@@ -169,14 +224,22 @@ def pin_dense_agrees(lib, trials=800, seed=5):
     return bad
 
 
-ALL_PINS = [pin_hand_traces, pin_nw_at_infinite_x, pin_identical_prefix, pin_invariants,
-            pin_suffix_independence, pin_dense_agrees]
+ALL_PINS = [pin_hand_traces, pin_reading_vectors, pin_worked_record, pin_nw_at_infinite_x, pin_identical_prefix,
+            pin_invariants, pin_suffix_independence, pin_dense_agrees]
 
 
 # ---------------------------------------------------------------- tests
 def test_golden_file_parses():
     rows = read_golden()
     assert len(rows) >= 9
+    assert len(read_vectors()) == 18 and len(read_records()) == 2
+
+
+def test_reading_vectors_show_non_monotone_score_in_x():
+    # the stored example itself: T(X=2) = 12 > T(X=3) = 5 < T(X=4) = 16
+    rows = [r for r in read_vectors() if len(r[0]) == 43]
+    by_x = {X: want[0] for _, _, _, _, _, X, want in rows}
+    assert by_x[2] > by_x[3] < by_x[4]
 
 
 @pytest.mark.parametrize("pin", ALL_PINS, ids=lambda f: f.__name__)

@@ -119,3 +119,19 @@ def test_pair_set_unchanged_by_storing_a_read_reverse_complemented():
     flipped = S.find_seeds(codes, st.off, st.length, k=15, lo=3, hi=30)
     assert len(base) > 20
     assert set(zip(base["read_a"], base["read_b"])) == set(zip(flipped["read_a"], flipped["read_b"]))
+
+
+def test_oracle_imports_nothing_from_the_product():
+    # the oracle modules load and run in a process that never imports the
+    # product package, and the seed records use the C ABI's record layout
+    import subprocess
+    import sys
+    root = os.path.dirname(HERE)
+    code = ("import sys, numpy as np; import oracle, oracle.seeds as S; oracle.load();"
+            "c = np.array([0,1,2,3,0,1,2,3,0,1,2,3], np.uint8);"
+            "r = S.find_seeds(c, np.array([0, 6]), np.array([6, 6]), k=3, lo=1, hi=9);"
+            "assert len(r) == 1;"
+            "bad = [m for m in sys.modules if m.startswith('paper_2309_07270_amd')];"
+            "assert not bad, bad")
+    subprocess.run([sys.executable, "-c", code], cwd=root, check=True)
+    assert S.SEED_RECORD_DTYPE == W.RECORD_DTYPE
