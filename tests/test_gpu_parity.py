@@ -176,33 +176,57 @@ def test_class_hand_over_pool_overflow(xd):
     assert int(stats["stage_tasks"][4]) > 0   # the unbounded class ran
 
 
-@pytest.mark.parametrize("weights", [(1, -1, -1), (1, -2, -2), (2, -3, -2)])
+# Window classes by the widest live range of an extension (from the oracle):
+# the adaptive windows hold bands up to 252 slots, the first wide class up to
+# 1020, the second up to 2044; wider bands finish in the unbounded kernel.
+# Each case below sits at least 6 % away from those limits.
+CLASS_BRACKETS = ((0, 235), (275, 955), (1090, 1915), (2175, 1 << 30))
+WIDEN_NARROW_CASES = {
+    # weights: (read a, read b, X) per record, one or two records per class
+    (1, -1, -1): [(2, 1, 14), (0, 2, 25), (2, 3, 30), (2, 3, 300), (0, 1, 400), (2, 3, 1200), (0, 1, 1500)],
+    (1, -2, -2): [(0, 1, 190), (0, 1, 400), (0, 1, 500), (0, 1, 2000), (0, 1, 2500), (0, 1, 4000)],
+    (2, -3, -2): [(0, 2, 36), (1, 3, 50), (0, 1, 60), (2, 3, 500), (0, 1, 600), (2, 3, 2000), (0, 1, 2400)],
+}
+
+
+@pytest.mark.parametrize("weights", sorted(WIDEN_NARROW_CASES))
 def test_bands_widen_then_narrow(xd, weights):
     # A random 2.5-3.2 kb prefix, then 6 kb shared by every read.  Through
-    # the random part the band widens (up to 770-3050 cells for X = 150 ..
-    # 2000 at +1/-1/-1): the wide windows step up their ladders and hand over
-    # to wider classes.  In the shared part the band collapses to about X,
-    # so the windows step back down their ladders.  The three weight sets
-    # take the three step variants (sigma in 2-bit fields; match 1 with a
-    # wider sigma; general weights); X scales with the match weight.
+    # the random part the band widens: the windows step up their ladders and
+    # hand over to wider classes.  In the shared part the band collapses to
+    # about X, so the windows step back down.  The three weight sets take the
+    # three step variants (sigma in 2-bit fields; match 1 with a wider sigma;
+    # general weights).  Seeds sit at position 0, so every left extension is
+    # empty and every right extension runs the whole reads.  For each weight
+    # set the cases reach every class, and each class must complete exactly
+    # the extensions whose widest band (from the oracle) it holds.
     rng = np.random.Generator(np.random.PCG64(55))
     shared = rng.integers(0, 4, 6000).astype(np.uint8)
     reads = [np.concatenate([rng.integers(0, 4, n).astype(np.uint8), shared]) for n in (2500, 2600, 3200, 3000)]
     lens = [r.size for r in reads]
     store = W.ReadStore(np.concatenate(reads), np.concatenate([[0], np.cumsum(lens)[:-1]]), np.array(lens))
-    recs = np.zeros(6, W.RECORD_DTYPE)
-    recs["read_a"] = [0, 0, 2, 1, 0, 2]
-    recs["read_b"] = [1, 1, 3, 3, 3, 1]
+    cases = WIDEN_NARROW_CASES[weights]
+    recs = np.zeros(len(cases), W.RECORD_DTYPE)
+    recs["read_a"] = [c[0] for c in cases]
+    recs["read_b"] = [c[1] for c in cases]
     recs["k"] = 1
-    recs["x"] = np.array([150, 300, 300, 600, 1000, 2000]) * weights[0]
+    recs["x"] = [c[2] for c in cases]
     recs["match"], recs["mismatch"], recs["gap"] = weights
+    want = [0] * 4
+    for a, b, x in cases:
+        _, width = oracle.extend_band(reads[a][1:], reads[b][1:], *weights, x)
+        cls = [k for k, (lo, hi) in enumerate(CLASS_BRACKETS) if lo <= width <= hi]
+        assert len(cls) == 1, f"case {(a, b, x)}: widest band {width} too near a class limit"
+        want[cls[0]] += 1
+    assert all(want), want   # every class is reached
+    want[0] += len(cases)    # the empty left extensions
     ref, _ = oracle.batch(store.codes, store.off, store.length, recs)
     note(f"bands that widen through every window class, then narrow; weights {weights}")
     with xd.Context(store) as ctx:
         res, cells, st = ctx.run(recs, count_cells=True)
     assert_same(res, cells, ref)
-    tasks = [int(v) for v in st["stage_tasks"]]
-    assert tasks[2] + tasks[3] + tasks[4] > 0, tasks   # the wide classes ran
+    tasks = [int(v) for v in st["stage_tasks"][1:5]]
+    assert tasks == want, (tasks, want)
 
 
 def test_identical_reads_full_length(xd):

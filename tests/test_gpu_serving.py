@@ -1,8 +1,8 @@
 """Serving loop on the GPU: many producer threads submit batches to one
 context; admitted batches run concurrently on their own streams (continuous
-batching).  Each batch's results must be identical alone and in the mix
-(integer path: tolerance 0), and admission must apply back-pressure when the
-HBM budget is exhausted.
+batching).  Each batch's results must equal the CPU oracle's, field by field
+and in cell counts, both alone and in the mix (integer path: tolerance 0),
+and admission must apply back-pressure when the HBM budget is exhausted.
 """
 import sys
 import threading
@@ -11,14 +11,38 @@ import time
 import numpy as np
 import pytest
 
+import oracle
 from paper_2309_07270_amd import workload as W
 
 pytestmark = pytest.mark.gpu
+
+FIELDS = (("score", "score"), ("left_score", "left"), ("right_score", "right"), ("seed_score", "seed"),
+          ("a_begin", "a_begin"), ("a_end", "a_end"), ("b_begin", "b_begin"), ("b_end", "b_end"))
 
 
 def note(msg):
     print(f"[gpu-serving] {msg}", flush=True)
     sys.stdout.flush()
+
+
+def assert_oracle(res, cells, ref, what):
+    """res / cells of one batch against the oracle rows of the same records."""
+    for fg, fr in FIELDS:
+        g = res[fg].astype(np.int64)
+        r = ref[fr].astype(np.int64)
+        bad = np.flatnonzero(g != r)
+        assert bad.size == 0, f"{what}: {fg} differs at record {int(bad[0])}: gpu {int(g[bad[0]])} oracle {int(r[bad[0]])}"
+    if cells is not None:
+        want = (ref["cells_left"] + ref["cells_right"]).astype(np.uint64)
+        bad = np.flatnonzero(cells.astype(np.uint64) != want)
+        assert bad.size == 0, f"{what}: cells differ at record {int(bad[0])}"
+
+
+def oracle_rows(wl, idx):
+    """Oracle results of records wl.records[idx], computed once per distinct record."""
+    uniq, inv = np.unique(idx, return_inverse=True)
+    ref, _ = oracle.batch(wl.store.codes, wl.store.off, wl.store.length, wl.records[uniq])
+    return ref[inv]
 
 
 @pytest.fixture(scope="module")
@@ -36,7 +60,15 @@ def wl():
     return W.make_workload("c2", pairs=60000, genome=1_000_000)
 
 
-def test_alone_equals_mixed(xd, wl):
+@pytest.fixture(scope="module")
+def pool_ref(wl):
+    # the oracle over the whole 60,000-record pool (every batch below is a slice of it)
+    note("oracle over the 60,000-record pool")
+    ref, _ = oracle.batch(wl.store.codes, wl.store.off, wl.store.length, wl.records)
+    return ref
+
+
+def test_alone_equals_mixed(xd, wl, pool_ref):
     rng = np.random.default_rng(0)
     n_prod, per = 25, 3
     sizes = rng.integers(1000, 4000, size=n_prod * per)
@@ -69,7 +101,9 @@ def test_alone_equals_mixed(xd, wl):
     assert not errors, errors
     for i, (a, m) in enumerate(zip(alone, mixed)):
         assert m is not None, f"batch {i} missing"
-        assert np.array_equal(a[0], m[0]) and np.array_equal(a[1], m[1]), f"batch {i} differs"
+        ref = pool_ref[starts[i]:starts[i] + sizes[i]]
+        assert_oracle(a[0], a[1], ref, f"batch {i} alone")
+        assert_oracle(m[0], m[1], ref, f"batch {i} mixed")
 
 
 def test_wide_bands_alone_equals_mixed(xd):
@@ -109,12 +143,19 @@ def test_wide_bands_alone_equals_mixed(xd):
         for t in th:
             t.join(timeout=120)
     assert not errors, errors
+    note("oracle of the wide-band batches")
+    idx = np.concatenate([np.arange(s, s + z) for s, z in zip(starts, sizes)])
+    refs = oracle_rows(wl4, idx)
+    off = 0
     for i, (a, m) in enumerate(zip(alone, mixed)):
         assert m is not None, f"batch {i} missing"
-        assert np.array_equal(a[0], m[0]) and np.array_equal(a[1], m[1]), f"batch {i} differs"
+        ref = refs[off:off + sizes[i]]
+        off += sizes[i]
+        assert_oracle(a[0], a[1], ref, f"wide batch {i} alone")
+        assert_oracle(m[0], m[1], ref, f"wide batch {i} mixed")
 
 
-def test_admission_backpressure_and_timeouts(xd, wl):
+def test_admission_backpressure_and_timeouts(xd, wl, pool_ref):
     recs = wl.records[:20000]
     big = np.tile(wl.records, 20)[:1 << 20]
     with xd.Context(wl.store) as probe:
@@ -131,7 +172,8 @@ def test_admission_backpressure_and_timeouts(xd, wl):
         t2, out2, _ = ctx.submit(recs, admit_timeout_us=-1)
         ctx.wait(t1)
         ctx.wait(t2)
-        assert np.array_equal(out1[:20000], out2)
+        assert_oracle(out1, None, pool_ref[:30000], "first batch")
+        assert_oracle(out2, None, pool_ref[:20000], "batch admitted after back-pressure")
         # a batch that can never fit is refused outright
         with pytest.raises(xd.XdropError) as e:
             ctx.submit(big)
@@ -174,9 +216,9 @@ def test_overlap_on_device(xd, wl):
     assert overlapped < serial
 
 
-def test_sub_batch_hand_off_equals_whole(xd, wl):
+def test_sub_batch_hand_off_equals_whole(xd, wl, pool_ref):
     """A producer batch handed over as sub-batches (submitted back to back,
-    waited together) gives the same results as the whole batch."""
+    waited together) gives the oracle's results, as the whole batch does."""
     recs = wl.records[5000:17000]
     note("12,000 records whole vs 5 sub-batches of 2,500 (last 2,000)")
     with xd.Context(wl.store, max_inflight=4) as ctx:
@@ -186,4 +228,6 @@ def test_sub_batch_hand_off_equals_whole(xd, wl):
             ctx.wait(t)
     split = np.concatenate([p[1] for p in parts])
     cs = np.concatenate([p[2] for p in parts])
-    assert np.array_equal(whole, split) and np.array_equal(cw, cs)
+    ref = pool_ref[5000:17000]
+    assert_oracle(whole, cw, ref, "whole batch")
+    assert_oracle(split, cs, ref, "sub-batches")
