@@ -212,6 +212,38 @@ xdrop_status xdrop_autotune(xdrop_ctx *c, const xdrop_record *recs, size_t n, co
  * including the unbounded kernel's scratch).  0 for a NULL context. */
 uint64_t xdrop_batch_footprint(const xdrop_ctx *c, size_t n);
 
+/* ---- Batches without allocation -----------------------------------------
+ * For callers that cannot allocate: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  The same computation as
+ * xdrop_batch_submit_device in the persistent form (same kernels and
+ * results), but no call of the library allocates anything on its behalf:
+ * every buffer a batch needs besides its records and results lives in one
+ * array of XDROP_NOALLOC_BYTES of device memory that the library holds on
+ * each GPU it is loaded on until the process ends.
+ *   d_recs:    n records in device memory of the context's GPU (read only);
+ *   d_out:     n results, device memory (written);
+ *   d_cells:   nullable, n uint64 per-record cell counts (device memory);
+ *   d_invalid: nullable, one uint32 in device memory: the number of invalid
+ *              records (their result rows are zero-filled, as in
+ *              xdrop_batch_submit_device);
+ *   stream:    hipStream_t of the context's GPU the kernels are launched on
+ *              (NULL: the null stream).
+ * The call only enqueues work and returns: nothing is ready until the stream
+ * reaches it, and there is no ticket or wait (no stats).  Every argument
+ * buffer, and the context (its read store), must stay valid until then.
+ * Errors: XDROP_E_INVALID for n > XDROP_NOALLOC_MAX_RECORDS, for reads so
+ * long that one workgroup's scratch of the unbounded-band kernel does not
+ * fit the array's share for it (reads over about 2 million bases), or a NULL
+ * buffer with n > 0; XDROP_E_DEVICE when the array's device address cannot
+ * be found or a launch fails.  All calls on one GPU share its array, and it
+ * keeps the last call's contents: calls whose work overlaps on one GPU
+ * (different streams, threads or contexts) race and give wrong results, so
+ * order them on one stream or synchronize between them. */
+#define XDROP_NOALLOC_BYTES (128ull << 20)
+#define XDROP_NOALLOC_MAX_RECORDS (1u << 19)
+xdrop_status xdrop_batch_run_noalloc(xdrop_ctx *c, const xdrop_record *d_recs, size_t n, xdrop_result *d_out,
+                                     uint64_t *d_cells, uint32_t *d_invalid, void *stream);
+
 /* ---- Seed discovery (the step before the batches) ------------------------
  * Records for the read pairs of the context's store that share a reliable
  * k-mer (paper, "Related works": BELLA detects overlaps from shared k-mers

@@ -717,6 +717,111 @@ void apply_tuning(xdrop_ctx *c, const Tuning &t)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Batch buffers without allocation (xdrop_batch_run_noalloc).  Every buffer a
+// batch needs beyond its records and results -- seed scores, validity flags,
+// task results, class queues, counters, bucket histograms, the carry pool and
+// the unbounded kernel's scratch -- is carved, per call, out of one array in
+// device memory that the code object holds for the life of the process (one
+// copy per GPU).  Host code never uses the array's name as an address: its
+// device address is looked up once per device with hipGetSymbolAddress at
+// context creation and kept in noalloc_base.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocBytes = XDROP_NOALLOC_BYTES;
+constexpr size_t kNoAllocGenericBytes = 24ull << 20;   // unbounded-kernel scratch share
+constexpr int kNoAllocMaxDevices = 64;
+static_assert(kNoAllocBytes % 256 == 0, "array size");
+
+std::mutex g_noalloc_mu;
+void *g_noalloc_base[kNoAllocMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char noalloc_scratch[kNoAllocBytes];
+
+namespace {
+
+// Device address of this device's copy of noalloc_scratch (the device must be
+// current); looked up once per device.
+bool noalloc_resolve(int device, std::string &why)
+{
+    if (device < 0 || device >= kNoAllocMaxDevices) {
+        why = "device ordinal beyond the no-alloc table";
+        return false;
+    }
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_base[device]) return true;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        why = std::string("hipGetSymbolAddress(noalloc_scratch): ") + hipGetErrorString(e);
+        return false;
+    }
+    g_noalloc_base[device] = p;
+    return true;
+}
+
+void *noalloc_base(int device)
+{
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    return device >= 0 && device < kNoAllocMaxDevices ? g_noalloc_base[device] : nullptr;
+}
+
+// The buffers of one no-alloc batch of n records (records, results and cell
+// counts are the caller's), laid out from `base`: the per-record arrays as in
+// a slot of capacity n, then counters, histograms and stage sums, then the
+// unbounded kernel's scratch (as many workgroups as fit its share, at most
+// the tuned count), then the carry pool in what is left (at most 256 words
+// per record; a smaller pool only makes more handed-over tasks restart).
+// Returns false with `why` set when the batch does not fit the array.
+bool noalloc_layout(const xdrop_ctx *c, const Tuning &tu, char *base, uint32_t n, BatchDev &b, GenericScratch &gs,
+                    std::string &why)
+{
+    if (n > XDROP_NOALLOC_MAX_RECORDS) {
+        why = "batch of " + std::to_string(n) + " records exceeds the no-alloc limit of " +
+              std::to_string(XDROP_NOALLOC_MAX_RECORDS);
+        return false;
+    }
+    size_t off = 0;
+    auto take = [&](size_t x) {
+        char *q = base + off;
+        off += (x + 255) & ~size_t(255);
+        return (void *)q;
+    };
+    const size_t cap = n;
+    b = BatchDev{};
+    b.seed = (int32_t *)take(cap * sizeof(int32_t));
+    b.valid = (uint8_t *)take(cap);
+    b.tout = (TaskOut *)take(2 * cap * sizeof(TaskOut));
+    b.qbuf = (uint32_t *)take((size_t)kNumClasses * 2 * cap * sizeof(uint32_t));
+    b.qkey = (uint32_t *)take((size_t)kNumClasses * 2 * cap * sizeof(uint32_t));
+    b.qstate = (uint32_t *)take((size_t)kNumClasses * 2 * cap * sizeof(uint32_t));
+    b.ctr = (uint32_t *)take(CtrLayout::kWords * sizeof(uint32_t) + 64);
+    b.bucket_hist = (uint32_t *)take((size_t)kNumClasses * kNumBuckets * sizeof(uint32_t));
+    b.stage_sum = (unsigned long long *)take(kStageSumWords * sizeof(unsigned long long));
+    b.cap = n;
+    const uint64_t stride = scratch_stride_of(c);
+    const uint64_t per_block = 3 * stride * sizeof(int32_t);
+    const uint64_t fit = kNoAllocGenericBytes / per_block;
+    if (fit == 0) {
+        why = "reads too long for the no-alloc buffer: the unbounded kernel needs " + std::to_string(per_block) +
+              " bytes per workgroup, its share is " + std::to_string(kNoAllocGenericBytes);
+        return false;
+    }
+    gs.blocks = (uint32_t)std::min<uint64_t>(generic_blocks(tu.generic_waves), fit);
+    gs.stride = stride;
+    gs.base = (int32_t *)take((size_t)gs.blocks * per_block);
+    if (off > kNoAllocBytes) {   // cannot happen within the record limit; checked all the same
+        why = "no-alloc layout exceeds the array";
+        return false;
+    }
+    const uint64_t left_words = (kNoAllocBytes - off) / sizeof(int32_t);
+    b.carry_words = (uint32_t)std::min<uint64_t>({left_words, (uint64_t)n * 256u, 64ull << 20});
+    b.carry = (int32_t *)(base + off);
+    return true;
+}
+
 bool write_tuning(const std::string &path, const Tuning &t)
 {
     std::ofstream f(path);
@@ -841,6 +946,11 @@ xdrop_status xdrop_batch_create(const xdrop_config *cfg, xdrop_ctx **out)
         hipDeviceProp_t prop;
         HIP_TRY(hipGetDeviceProperties(&prop, c->device));
         c->cus = prop.multiProcessorCount;
+        // device address of this GPU's no-alloc buffer, looked up once per
+        // device with it current; a failure is reported by the no-alloc entry
+        // point (which tries again) and does not affect the other calls
+        std::string why;
+        if (!noalloc_resolve(c->device, why)) set_global_error(why);
         HIP_TRY(hipMalloc(&c->d_words, nwords * sizeof(uint32_t)));
         HIP_TRY(hipMalloc(&c->d_reads, (size_t)nr * sizeof(ReadInfo)));
         HIP_TRY(hipMemcpy(c->d_words, words.data(), nwords * sizeof(uint32_t), hipMemcpyHostToDevice));
@@ -1051,6 +1161,59 @@ xdrop_status xdrop_autotune(xdrop_ctx *c, const xdrop_record *recs, size_t n, co
         }
     }
     if (best_ms) *best_ms = best_t;
+    return XDROP_OK;
+}
+
+xdrop_status xdrop_batch_run_noalloc(xdrop_ctx *c, const xdrop_record *d_recs, size_t n, xdrop_result *d_out,
+                                     uint64_t *d_cells, uint32_t *d_invalid, void *stream)
+{
+    if (!c || (n && (!d_recs || !d_out))) return XDROP_E_INVALID;
+    Tuning tu;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        if (c->poisoned) return XDROP_E_DEVICE;
+        tu = c->tune;
+    }
+    if (n > XDROP_NOALLOC_MAX_RECORDS) {
+        c->fail("xdrop_batch_run_noalloc: batch of " + std::to_string(n) + " records exceeds the limit of " +
+                std::to_string(XDROP_NOALLOC_MAX_RECORDS));
+        return XDROP_E_INVALID;
+    }
+    std::string why;
+    if (hipSetDevice(c->device) != hipSuccess) {
+        (void)hipGetLastError();
+        c->fail("xdrop_batch_run_noalloc: hipSetDevice failed");
+        return XDROP_E_DEVICE;
+    }
+    if (!noalloc_resolve(c->device, why)) {
+        c->fail("xdrop_batch_run_noalloc: " + why);
+        return XDROP_E_DEVICE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    BatchDev b{};
+    GenericScratch gs{};
+    if (!noalloc_layout(c, tu, (char *)noalloc_base(c->device), (uint32_t)n, b, gs, why)) {
+        c->fail("xdrop_batch_run_noalloc: " + why);
+        return XDROP_E_INVALID;
+    }
+    b.recs = d_recs;
+    b.res = d_out;
+    b.cells = d_cells;
+    try {
+        // the persistent form's kernel sequence, launched directly on the
+        // caller's stream (no graph, no events); the batch size is immediate.
+        // An empty batch only clears the counters (the invalid count is 0).
+        if (n == 0)
+            launch_reset_n(b, nullptr, 0u, s);
+        else
+            enqueue_kernels(c, tu, gs, b, (uint32_t)n, nullptr, true, d_cells != nullptr, s, nullptr);
+        if (d_invalid)
+            HIP_TRY(hipMemcpyAsync(d_invalid, b.ctr + CtrLayout::kErrors, sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipGetLastError());
+    } catch (const std::exception &e) {
+        c->fail(std::string("xdrop_batch_run_noalloc: ") + e.what());
+        return XDROP_E_DEVICE;
+    }
     return XDROP_OK;
 }
 

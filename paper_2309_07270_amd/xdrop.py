@@ -27,9 +27,13 @@ MODE_PERSISTENT = 0
 MODE_PLAIN = 1
 MAX_X = 1 << 30
 
+NOALLOC_BYTES = 128 << 20
+NOALLOC_MAX_RECORDS = 1 << 19
+
 EXPORTED = ("xdrop_batch_create", "xdrop_batch_submit", "xdrop_batch_submit_device", "xdrop_batch_wait",
             "xdrop_batch_destroy", "xdrop_batch_footprint", "xdrop_get_tuning", "xdrop_set_tuning",
-            "xdrop_autotune", "xdrop_find_seeds", "xdrop_status_string", "xdrop_last_error")
+            "xdrop_autotune", "xdrop_find_seeds", "xdrop_status_string", "xdrop_last_error",
+            "xdrop_batch_run_noalloc")
 
 
 class Config(ctypes.Structure):
@@ -104,6 +108,8 @@ def load_library(path: str = LIB_PATH):
     lib.xdrop_batch_submit.argtypes = [vp, vp, ctypes.c_size_t, vp, vp, ctypes.c_int64, P(ctypes.c_uint64)]
     lib.xdrop_batch_submit_device.argtypes = [vp, vp, ctypes.c_size_t, vp, vp, vp, P(ctypes.c_uint64)]
     lib.xdrop_batch_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_int64, P(Stats)]
+    lib.xdrop_batch_run_noalloc.argtypes = [vp, vp, ctypes.c_size_t, vp, vp, vp, vp]
+    lib.xdrop_batch_run_noalloc.restype = ctypes.c_int
     lib.xdrop_batch_destroy.argtypes = [vp]
     lib.xdrop_status_string.argtypes = [ctypes.c_int]
     lib.xdrop_status_string.restype = ctypes.c_char_p
@@ -283,6 +289,15 @@ class Context:
         self._check(st)
         self._pending[t.value] = (d_recs, d_out, d_cells)
         return t.value
+
+    def run_noalloc(self, d_recs, n: int, d_out, d_cells=None, d_invalid=None, stream=None) -> None:
+        """Enqueue one device batch on `stream` through the entry point that
+        allocates nothing (xdrop_batch_run_noalloc); results are ready when the
+        stream reaches the work.  Buffers: torch tensors or device pointers."""
+        sp = None if stream is None else int(getattr(stream, "cuda_stream", stream))
+        self._check(self.lib.xdrop_batch_run_noalloc(self.h, _ptr(d_recs), n, _ptr(d_out),
+                                                     _ptr(d_cells) if d_cells is not None else None,
+                                                     _ptr(d_invalid) if d_invalid is not None else None, sp))
 
 
 def status_string(st: int) -> str:
