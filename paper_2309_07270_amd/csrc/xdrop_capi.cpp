@@ -181,7 +181,9 @@ Tuning default_tuning()
     t.shrink_margin = 6;
     t.waves_per_cu = 32;
     t.buckets = 1;
-    t.generic_waves = 64 * kGenericBlockWaves;   // 64 extensions of unbounded band at once
+    // 256 extensions of unbounded band at once (one workgroup per CU: each
+    // holds a 96 KB LDS ring); fewer when their scratch would pass 256 MiB
+    t.generic_waves = 256 * kGenericBlockWaves;
     return t;
 }
 
@@ -228,12 +230,15 @@ bool validate_host(const xdrop_ctx *c, const xdrop_record &R, std::string &why)
     return true;
 }
 
-// carry pool of a slot: 256 words per record of capacity (the c4 stress mix
-// hands about 0.16 extensions per record to the 2048-slot class, 2,064 words
-// each), at most 64 Mi words; a full pool only makes tasks restart
+// carry pool of a slot: 512 words per record of capacity, at most 1 Gi words
+// (4 GiB).  The c4 stress mix hands about 0.16 extensions per record to the
+// 2048-slot class, 2,064 words each (330 words per record), plus a few to
+// the unbounded kernel; a full pool only makes the remaining hand-overs
+// restart from the seed, which repeats most of an extension in a window far
+// wider than its early band
 uint32_t carry_words_for(uint32_t cap)
 {
-    return (uint32_t)std::min<uint64_t>((uint64_t)cap * 256u, 64ull << 20);
+    return (uint32_t)std::min<uint64_t>((uint64_t)cap * 512u, 1ull << 30);
 }
 
 size_t slot_bytes(uint32_t cap)
