@@ -79,22 +79,27 @@ enum {
 };
 
 /* Kernel stages reported in xdrop_batch_stats.stage_ms / stage_cells.  An
- * extension runs in the adaptive kernel first and moves to the next stage
- * only when its live band outgrows the current one: out of the adaptive
- * kernel it restarts from the seed; between the later stages it carries its
- * state over (restarting only when the batch's carry pool is full). */
+ * extension with a small drop (x <= the narrow_x tuning knob, persistent
+ * form) and weights match 1, gap -1, mismatch 0, -1 or -2 runs in the narrow
+ * kernel first; every other one in the adaptive kernel.  It moves to the
+ * next stage only when its live band outgrows the current one: out of the
+ * narrow and adaptive kernels it restarts from the seed; between the later
+ * stages it carries its state over (restarting only when the batch's carry
+ * pool is full). */
 enum {
     XDROP_STAGE_INGEST = 0,       /* counter reset, validation, seed, bucketing  */
-    XDROP_STAGE_ADAPTIVE = 1,     /* register window of 64..256 slots that
+    XDROP_STAGE_NARROW = 1,       /* two extensions per wavefront, windows of
+                                     32 or 64 slots over half the lanes     */
+    XDROP_STAGE_ADAPTIVE = 2,     /* register window of 64..256 slots that
                                      follows the band width                 */
-    XDROP_STAGE_WIDE1024 = 2,     /* register window of 512..1024 slots that
+    XDROP_STAGE_WIDE1024 = 3,     /* register window of 512..1024 slots that
                                      follows the band width                 */
-    XDROP_STAGE_WIDE2048 = 3,     /* register window of 1536..2048 slots    */
-    XDROP_STAGE_GENERIC = 4,      /* unbounded band: one workgroup per
+    XDROP_STAGE_WIDE2048 = 4,     /* register window of 1536..2048 slots    */
+    XDROP_STAGE_GENERIC = 5,      /* unbounded band: one workgroup per
                                      extension, LDS ring (global memory for
                                      bands over 8192 cells)                 */
-    XDROP_STAGE_FINALIZE = 5,     /* result write-back                      */
-    XDROP_NUM_STAGES = 6
+    XDROP_STAGE_FINALIZE = 6,     /* result write-back                      */
+    XDROP_NUM_STAGES = 7
 };
 
 #define XDROP_MAX_READ_LEN (1u << 24)
@@ -185,6 +190,9 @@ typedef struct {
     int32_t buckets;              /* 1: order extensions longest-first; 0: arrival order   */
     int32_t generic_waves;        /* grid of the unbounded-band kernel, in wavefronts: one
                                      workgroup of 16 per extension (multiple of 16)          */
+    int32_t narrow_x;             /* persistent form: records with x <= narrow_x and weights
+                                     match 1, gap -1, mismatch 0 / -1 / -2 run two extensions
+                                     per wavefront (narrow stage); -1: off; at most 64        */
 } xdrop_tuning;
 
 /* Current launch parameters of a context. */
@@ -197,7 +205,8 @@ xdrop_status xdrop_set_tuning(xdrop_ctx *c, const xdrop_tuning *t);
 /* Autotuner: run the n host records (a representative sample, e.g. 10k-200k
  * records) under launch parameters chosen by coordinate descent -- each knob
  * (persistent grid size, length bucketing, adaptive window margins, grid of
- * the unbounded-band kernel) swept in turn with the others at the best so
+ * the unbounded-band kernel, drop bound of the two-extensions-per-wavefront
+ * narrow stage) swept in turn with the others at the best so
  * far, two rounds, each setting timed by the better of two runs after a
  * warm-up -- keep the fastest by device time and make it the context's
  * tuning.  Every setting gives the same results.  When cache_path is non-NULL the choice is

@@ -184,6 +184,7 @@ Tuning default_tuning()
     // 256 extensions of unbounded band at once (one workgroup per CU: each
     // holds a 96 KB LDS ring); fewer when their scratch would pass 256 MiB
     t.generic_waves = 256 * kGenericBlockWaves;
+    t.narrow_x = 20;
     return t;
 }
 
@@ -203,6 +204,8 @@ bool load_tuning(const std::string &path, Tuning &t)
             f >> t.buckets;
         } else if (key == "generic_waves") {
             f >> t.generic_waves;
+        } else if (key == "narrow_x") {
+            f >> t.narrow_x;
         } else {
             std::string rest;
             std::getline(f, rest);
@@ -393,23 +396,29 @@ struct GenericScratch {
 void enqueue_kernels(xdrop_ctx *c, const Tuning &tu, const GenericScratch &gs, const BatchDev &b, uint32_t n,
                      const uint32_t *n_src, bool persistent, bool count, hipStream_t s, hipEvent_t *ev)
 {
-    // ev (nullable): kNumStages + 1 stage-boundary events recorded between the launches
+    // ev (nullable): kNumStages + 1 stage-boundary events recorded between the
+    // launches; ev[1 + k] after class k
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     launch_reset_n(b, n_src, n, s);
     const bool stage = persistent && tu.buckets > 0;
-    launch_prep(b, c->st, tu, n, stage, s);
+    // the plain form runs one wavefront per extension: no narrow class
+    Tuning tp = tu;
+    if (!persistent) tp.narrow_x = -1;
+    launch_prep(b, c->st, tp, n, stage, s);
     if (stage) launch_bucket(b, c->st, n, s);
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     const uint32_t resident = (uint32_t)c->cus * (uint32_t)std::max(1, tu.waves_per_cu);
-    // plain form: one wavefront per extension for the first class
+    if (tp.narrow_x >= 0) launch_narrow(b, c->st, tu, resident, count, s);
+    if (ev) HIP_TRY(hipEventRecord(ev[2 + kNarrowClass], s));
+    // plain form: one wavefront per extension
     launch_adaptive(b, c->st, tu, persistent ? resident : std::max<uint32_t>(2 * n, 4), count, s);
-    if (ev) HIP_TRY(hipEventRecord(ev[2], s));
+    if (ev) HIP_TRY(hipEventRecord(ev[2 + kAdaptiveClass], s));
     for (int w = 0; w < kWideClasses; ++w) {
         launch_wide(w, b, c->st, (uint32_t)c->cus * 8u, count, s);
-        if (ev) HIP_TRY(hipEventRecord(ev[3 + w], s));
+        if (ev) HIP_TRY(hipEventRecord(ev[2 + kAdaptiveClass + 1 + w], s));
     }
     launch_generic(b, c->st, gs.base, gs.stride, gs.blocks, count, s);
-    if (ev) HIP_TRY(hipEventRecord(ev[2 + kNumClasses - 1], s));
+    if (ev) HIP_TRY(hipEventRecord(ev[2 + kGenericClass], s));
     launch_finalize(b, c->st, n, count, s);
     if (ev) HIP_TRY(hipEventRecord(ev[kNumStages], s));
 }
@@ -701,6 +710,7 @@ void clamp_tuning(Tuning &t)
     t.buckets = t.buckets ? 1 : 0;
     t.generic_waves = (std::min(std::max(t.generic_waves, kGenericBlockWaves), 4096) + kGenericBlockWaves - 1) /
                       kGenericBlockWaves * kGenericBlockWaves;
+    t.narrow_x = std::min(std::max(t.narrow_x, -1), kNarrowMaxX);
 }
 
 // new launch parameters: captured graphs hold the old ones; the unbounded
@@ -835,7 +845,8 @@ bool write_tuning(const std::string &path, const Tuning &t)
       << "shrink_margin " << t.shrink_margin << "\n"
       << "waves_per_cu " << t.waves_per_cu << "\n"
       << "buckets " << t.buckets << "\n"
-      << "generic_waves " << t.generic_waves << "\n";
+      << "generic_waves " << t.generic_waves << "\n"
+      << "narrow_x " << t.narrow_x << "\n";
     return (bool)f;
 }
 
@@ -1054,6 +1065,7 @@ xdrop_status xdrop_get_tuning(const xdrop_ctx *c, xdrop_tuning *out)
     out->waves_per_cu = c->tune.waves_per_cu;
     out->buckets = c->tune.buckets;
     out->generic_waves = c->tune.generic_waves;
+    out->narrow_x = c->tune.narrow_x;
     return XDROP_OK;
 }
 
@@ -1068,6 +1080,7 @@ xdrop_status xdrop_set_tuning(xdrop_ctx *c, const xdrop_tuning *in)
     t.waves_per_cu = in->waves_per_cu;
     t.buckets = in->buckets;
     t.generic_waves = in->generic_waves;
+    t.narrow_x = in->narrow_x;
     clamp_tuning(t);
     try {
         apply_tuning(c, t);
@@ -1127,6 +1140,9 @@ xdrop_status xdrop_autotune(xdrop_ctx *c, const xdrop_record *recs, size_t n, co
          [](Tuning &t, std::pair<int, int> v) { t.grow_margin = v.first; t.shrink_margin = v.second; }},
         {{{256, 0}, {1024, 0}, {4096, 0}},
          [](Tuning &t, std::pair<int, int> v) { t.generic_waves = v.first; }},
+        // two extensions per wavefront for drops up to: off, 15, 20, 30, 40
+        {{{-1, 0}, {15, 0}, {20, 0}, {30, 0}, {40, 0}},
+         [](Tuning &t, std::pair<int, int> v) { t.narrow_x = v.first; }},
     };
     const Tuning start = c->tune;
     Tuning best = start;

@@ -32,20 +32,28 @@ struct TaskOut {
 // Extension kernels ("classes"), tried in order; a task whose live band
 // outgrows a class moves to the next one (a wide class hands over its state
 // when the carry pool has room; otherwise the task restarts there):
-//   0  adaptive register window, 1..4 cells per lane (64..256 slots), the
+//   0  narrow bands (small drops): two extensions per wavefront, each in a
+//      window of 32 or 64 slots over one half of the lanes;
+//   1  adaptive register window, 1..4 cells per lane (64..256 slots), the
 //      width following the band;
-//   1  register window of 8, 12 or 16 cells per lane (512..1024 slots), the
+//   2  register window of 8, 12 or 16 cells per lane (512..1024 slots), the
 //      width following the band;
-//   2  register window of 24 or 32 cells per lane (1536..2048 slots);
-//   3  unbounded band: one workgroup per extension, anti-diagonals in an LDS
+//   3  register window of 24 or 32 cells per lane (1536..2048 slots);
+//   4  unbounded band: one workgroup per extension, anti-diagonals in an LDS
 //      ring (global memory beyond 8192 cells).
-constexpr int kAdaptiveClass = 0;
+constexpr int kNarrowClass = 0;
+constexpr int kAdaptiveClass = 1;
 constexpr int kWideClasses = 2;
 constexpr int kWideC[kWideClasses] = {16, 32};   // widest window of each wide class, cells per lane
-constexpr int kGenericClass = 1 + kWideClasses;
+constexpr int kGenericClass = kAdaptiveClass + 1 + kWideClasses;
 constexpr int kNumClasses = kGenericClass + 1;
 constexpr int kNumStages = kNumClasses + 2;   // ingest, classes..., finalize
+static_assert(kNumStages == XDROP_NUM_STAGES, "stages of the public statistics");
 constexpr int kNumBuckets = 64;
+// narrow class: drops up to this bound by default, when the weights allow
+// (match 1, gap -1, mismatch 0, -1 or -2); larger values of the tuning knob
+// are clamped to it
+constexpr int kNarrowMaxX = 64;
 
 // Device buffers of one batch (all device pointers).
 constexpr int kStageSumWords = 24;
@@ -112,6 +120,7 @@ struct Tuning {
     int32_t waves_per_cu;                   // persistent grid size per class kernel
     int32_t buckets;                        // 0: no length bucketing
     int32_t generic_waves;                  // grid of the unbounded kernel
+    int32_t narrow_x;                       // narrow class for drops <= narrow_x (-1: off)
 };
 
 // Kernel launchers (xdrop_kernels.hip).  All are asynchronous on `s`.
@@ -121,6 +130,8 @@ void launch_accum_errors(const BatchDev &b, uint32_t *acc, hipStream_t s);
 void launch_prep(const BatchDev &b, const StoreDev &st, const Tuning &tu, uint32_t n,
                  bool stage, hipStream_t s);
 void launch_bucket(const BatchDev &b, const StoreDev &st, uint32_t n, hipStream_t s);
+void launch_narrow(const BatchDev &b, const StoreDev &st, const Tuning &tu, uint32_t grid_waves, bool count_cells,
+                   hipStream_t s);
 void launch_adaptive(const BatchDev &b, const StoreDev &st, const Tuning &tu, uint32_t grid_waves,
                      bool count_cells, hipStream_t s);
 void launch_wide(int which, const BatchDev &b, const StoreDev &st, uint32_t grid_waves, bool count_cells,

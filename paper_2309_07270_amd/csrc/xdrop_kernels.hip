@@ -11,7 +11,9 @@
 // Layout on the device:
 //   * reads: 2 bits per base, both orientations, in one word array;
 //   * in the window kernels one wavefront runs one extension (task); all
-//     control is wave-uniform and lives in SGPRs;
+//     control is wave-uniform and lives in SGPRs.  The narrow class (small
+//     drops) runs two extensions per wavefront, one per half of the lanes,
+//     with the per-half control in pairs of SGPRs and per-lane thresholds;
 //   * window kernels: the live band of anti-diagonals d-1 and d-2 is held in
 //     VGPRs, 64 lanes x C cells, indexed by slot s = C*lane + r with
 //     i = o_d + s and o_d = base + floor(d/2).  With that origin the diagonal
@@ -247,7 +249,10 @@ __global__ void __launch_bounds__(256) prep_kernel(BatchDev b, StoreDev st, Tuni
             mism += (uint32_t)__builtin_popcount(x);
         }
         b.seed[r] = (int)(R.k - mism) * R.match + (int)mism * R.mismatch;
-        cls = kAdaptiveClass;
+        // small drops with match 1, gap -1 and mismatch 0 / -1 / -2: two
+        // extensions per wavefront (narrow class)
+        const bool narrow = R.x <= tu.narrow_x && R.match == 1 && R.gap == -1 && R.mismatch >= -2;
+        cls = narrow ? kNarrowClass : kAdaptiveClass;
         key0 = min(R.pos_a, pb);
         key1 = min(A.len - R.pos_a - R.k, B.len - pb - R.k);
     }
@@ -884,15 +889,601 @@ __device__ bool run_adaptive(const uint32_t *__restrict__ W, const Task &k, int 
     }
 }
 
-// Class 0: adaptive windows.  Tasks whose band outgrows 256 cells go to class 1.
-// Registers capped for 6 wavefronts per SIMD (the compiler's own choice
-// allows 5; the cap costs one spill at entry and its reload per task).
+// ---------------------------------------------------------------------------
+// Narrow class: two extensions per wavefront.
+//
+// Small drops keep small bands: at X = 20 and 15 % error an extension holds
+// about 20 live cells, a third of a 64-lane window.  Here each half of the
+// wavefront (a "group" of 32 lanes) runs its own extension in a window of
+// 32*C slots, C = 1 or 2 cells per lane (the same for both groups): slot
+// s = C*(lane & 31) + r of the group, cell i = o_d + s as in Window.  The
+// groups step together, one anti-diagonal of each per step and both at the
+// same parity, so one step is the instruction sequence of one window: one
+// 64-lane DPP rotate feeds the gap predecessors of both groups (the value it
+// moves across the middle comes from an edge slot, which band control keeps
+// dead as at the wave's ends).  What differs per group lives per lane
+// (thresholds, drop, clipping bounds, sigma fields) or in a pair of SGPRs
+// (band control, end cell, sequences).
+//
+// Only weights with match 1 and gap -1 (mismatch 0, -1 or -2) come here: an
+// improving cell then holds exactly T + 1, so each group's threshold rises
+// by 1 + (improvement) per anti-diagonal -- one v_addc per step for both
+// groups, fed by a per-group "improved" mask built on the scalar unit.  A
+// group whose extension ends takes the next task at the start of the next
+// block (blocks start at odd anti-diagonals, as every extension does); a
+// band wider than a 64-slot window sends its task to the adaptive class,
+// where it restarts.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kNoTask = 0xffffffffu;
+
+// Wave-uniform state of the extension of one group.
+struct GroupX {
+    uint32_t t;          // task, kNoTask when the group is empty
+    int d, base;         // next anti-diagonal; slot 0 of anti-diagonal d holds i = base + floor(d/2)
+    int bi, bj;          // best cell so far (the best score is the group's threshold minus d)
+    int m, n, x, sx;     // lengths, drop, sigma - 2*gap of a mismatch (a match: 3)
+    uint64_t abase, bbase;
+    uint64_t cells, slots;
+    uint32_t li;         // group lanes that improved at the group's last improving step of the half
+    int lu;              // that step's offset in the half (-1: none)
+    int mn, mx;          // live slots over the last two anti-diagonals (set at block starts)
+};
+
+constexpr int kNarrowSm = 3;   // sigma - 2*gap of a match (match 1, gap -1)
+
+template <int C, bool COUNT>
+struct PairWin {
+    static constexpr int WIN = 32 * C;                 // slots per group
+    static constexpr int PB = 2 * UMAX;                // pairs per block: two halves per load of codes
+    static constexpr int NWC = (C + PB + 16) / 16;     // words of codes per lane and block
+    static constexpr int STRIDE = 128;                 // LDS slots per anti-diagonal (two groups of <= 64)
+    // edge slots 0, 1, WIN-2, WIN-1 of both groups
+    static constexpr uint64_t EDGE = C == 1 ? 0xC0000003C0000003ull : 0x8000000180000001ull;
+
+    int Z1[C], Z2[C];               // anti-diagonals d-1 and d-2 in Z units (S + d); NEG = dead
+    uint32_t mmo[C], mme[C];        // sigma'' fields of the pairs of the current half
+    uint32_t mmo2[C], mme2[C];      // the same for the second half
+    int rs;                         // C = 2: first improving r of this lane at its group's last improving step
+
+    __device__ __forceinline__ void clear()
+    {
+#pragma unroll
+        for (int r = 0; r < C; ++r) { Z1[r] = NEG; Z2[r] = NEG; }
+        rs = 0;
+    }
+
+    // lanes of group g: a fresh extension (only (0,0) live, in the middle
+    // slot) or, fresh = false, all dead
+    __device__ __forceinline__ void set_group(int g, bool fresh)
+    {
+        const int lane = lane_id();
+        const bool mine = (lane >> 5) == g;
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            const int s = C * (lane & 31) + r;
+            Z1[r] = mine ? ((fresh && s == WIN / 2 - 1) ? 0 : NEG) : Z1[r];
+            Z2[r] = mine ? NEG : Z2[r];
+        }
+    }
+
+    __device__ __forceinline__ void save(int *lds) const
+    {
+        const int lane = lane_id();
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            lds[C * lane + r] = Z1[r];
+            lds[STRIDE + C * lane + r] = Z2[r];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
+    // take over windows of from_win slots per group saved in LDS: new slot s
+    // of a group holds its old slot s + dl (dl: this lane's group's shift)
+    __device__ __forceinline__ void load(const int *lds, int from_win, int dl)
+    {
+        const int lane = lane_id(), g = lane >> 5;
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            const int s = C * (lane & 31) + r + dl;
+            const bool ok = s >= 0 && s < from_win;
+            const int idx = g * from_win + (ok ? s : 0);
+            const int a = lds[idx], b2 = lds[STRIDE + idx];
+            Z1[r] = ok ? a : NEG;
+            Z2[r] = ok ? b2 : NEG;
+        }
+        rs = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
+    // live slots of each group over the last two anti-diagonals
+    __device__ __forceinline__ void bands(GroupX &g0, GroupX &g1) const
+    {
+        g0.mn = g1.mn = 1 << 30;
+        g0.mx = g1.mx = -1;
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            const uint64_t u = ballot(max(Z1[r], Z2[r]) > NEG_HALF);
+            const uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
+            if (lo) {
+                g0.mn = min(g0.mn, C * __builtin_ctz(lo) + r);
+                g0.mx = max(g0.mx, C * (31 - __builtin_clz(lo)) + r);
+            }
+            if (hi) {
+                g1.mn = min(g1.mn, C * __builtin_ctz(hi) + r);
+                g1.mx = max(g1.mx, C * (31 - __builtin_clz(hi)) + r);
+            }
+        }
+    }
+
+    __device__ __forceinline__ bool alive() const
+    {
+        int z = NEG;
+#pragma unroll
+        for (int r = 0; r < C; ++r) z = max(z, max(Z1[r], Z2[r]));
+        return ballot(z > NEG_HALF) != 0;
+    }
+
+    // Per group: keep the improvement mask and step offset `so` of this step
+    // when the group improved; returns the lanes of the groups that improved.
+    template <int SO>
+    __device__ __forceinline__ static uint64_t record(GroupX &g0, GroupX &g1, uint64_t imp, uint32_t so_rt)
+    {
+        const uint32_t ilo = (uint32_t)imp, ihi = (uint32_t)(imp >> 32);
+        uint32_t mlo, mhi;
+        if (SO >= 0) {
+            asm volatile("s_cmp_lg_u32 %[ilo], 0\n\t"
+                         "s_cselect_b32 %[li0], %[ilo], %[li0]\n\t"
+                         "s_cselect_b32 %[lu0], %[so], %[lu0]\n\t"
+                         "s_cselect_b32 %[mlo], -1, 0\n\t"
+                         "s_cmp_lg_u32 %[ihi], 0\n\t"
+                         "s_cselect_b32 %[li1], %[ihi], %[li1]\n\t"
+                         "s_cselect_b32 %[lu1], %[so], %[lu1]\n\t"
+                         "s_cselect_b32 %[mhi], -1, 0"
+                         : [li0] "+s"(g0.li), [lu0] "+s"(g0.lu), [li1] "+s"(g1.li), [lu1] "+s"(g1.lu),
+                           [mlo] "=&s"(mlo), [mhi] "=&s"(mhi)
+                         : [ilo] "s"(ilo), [ihi] "s"(ihi), [so] "i"(SO < 0 ? 0 : SO)
+                         : "scc");
+        } else {
+            asm volatile("s_cmp_lg_u32 %[ilo], 0\n\t"
+                         "s_cselect_b32 %[li0], %[ilo], %[li0]\n\t"
+                         "s_cselect_b32 %[lu0], %[so], %[lu0]\n\t"
+                         "s_cselect_b32 %[mlo], -1, 0\n\t"
+                         "s_cmp_lg_u32 %[ihi], 0\n\t"
+                         "s_cselect_b32 %[li1], %[ihi], %[li1]\n\t"
+                         "s_cselect_b32 %[lu1], %[so], %[lu1]\n\t"
+                         "s_cselect_b32 %[mhi], -1, 0"
+                         : [li0] "+s"(g0.li), [lu0] "+s"(g0.lu), [li1] "+s"(g1.li), [lu1] "+s"(g1.lu),
+                           [mlo] "=&s"(mlo), [mhi] "=&s"(mhi)
+                         : [ilo] "s"(ilo), [ihi] "s"(ihi), [so] "s"(so_rt)
+                         : "scc");
+        }
+        return ((uint64_t)mhi << 32) | mlo;
+    }
+
+    // One anti-diagonal of both groups.  ub: bit offset 2u of the pair in the
+    // sigma words (KU >= 0: the constant KU); ti / tp: this lane's group's
+    // improvement and drop thresholds in Z units, on return those of the next
+    // anti-diagonal; lo_s / hi_s (BOUNDS): this lane's group's candidate
+    // slots.  Returns the live-cell mask of the step (edge lanes tested by
+    // the caller).
+    template <bool ODD, bool BOUNDS, int KU = -1>
+    __device__ __forceinline__ uint64_t step(GroupX &g0, GroupX &g1, uint32_t ub_rt, int &ti, int &tp, int xv,
+                                             int lo_s, int hi_s, uint32_t sinc0, uint32_t sinc1)
+    {
+        const uint32_t ub = KU >= 0 ? (uint32_t)KU : ub_rt;
+        const int lane = lane_id();
+        int t[C];
+        if (ODD) {
+            t[0] = max(__builtin_amdgcn_mov_dpp(Z1[C - 1], 0x13C, 0xf, 0xf, true), Z1[0]);   // wave_ror:1
+#pragma unroll
+            for (int r = 1; r < C; ++r) t[r] = max(Z1[r - 1], Z1[r]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < C - 1; ++r) t[r] = max(Z1[r], Z1[r + 1]);
+            t[C - 1] = max(__builtin_amdgcn_mov_dpp(Z1[0], 0x134, 0xf, 0xf, true), Z1[C - 1]);   // wave_rol:1
+        }
+        uint64_t imp = 0, imp0 = 0, lm = 0;
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            const uint32_t w = ODD ? mmo[r] : mme[r];
+            const int v = max(t[r], Z2[r] + (int)__builtin_amdgcn_ubfe(w, ub, 2u));
+            const int sl = C * (lane & 31) + r;
+            const uint64_t inbm = BOUNDS ? ballot(sl >= lo_s) & ballot(sl <= hi_s) : ~0ull;
+            const uint64_t ir = ballot(v > ti) & inbm;
+            if (r == 0) imp0 = ir;
+            imp |= ir;
+            if (COUNT) {
+                const uint64_t cm = ballot(v > NEG_HALF) & inbm;
+                g0.cells += (uint64_t)__builtin_popcount((uint32_t)cm);
+                g1.cells += (uint64_t)__builtin_popcount((uint32_t)(cm >> 32));
+            }
+            lm |= ballot(v >= tp) & inbm;
+            const bool keep = BOUNDS ? (sl >= lo_s && sl <= hi_s && v >= tp) : v >= tp;
+            t[r] = keep ? v : NEG;
+        }
+        if (COUNT) {
+            g0.slots += sinc0;
+            g1.slots += sinc1;
+        }
+        // step offset in the half: 2u on the odd step, 2u + 1 on the even one
+        uint64_t mg;
+        if (KU >= 0)
+            mg = record<KU < 0 ? 0 : (ODD ? KU : KU + 1)>(g0, g1, imp, 0u);
+        else
+            mg = record<-1>(g0, g1, imp, ODD ? ub : ub + 1u);
+        // ti += 1 + (this lane's group improved), tp = ti - x
+        uint64_t co;
+        asm("v_addc_co_u32_e64 %0, %1, %2, 1, %3" : "=v"(ti), "=s"(co) : "v"(ti), "s"(mg));
+        tp = ti - xv;
+        if (C > 1) {
+            const int rcur = ((imp0 >> lane) & 1ull) ? 0 : 1;
+            rs = ((mg >> lane) & 1ull) ? rcur : rs;
+        }
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            Z2[r] = Z1[r];
+            Z1[r] = t[r];
+        }
+        return lm;
+    }
+
+    // ub + 2, plus 64 when e has a live cell in an edge slot of either group
+    __device__ __forceinline__ static uint32_t next_pair(uint32_t ub, uint64_t e)
+    {
+        const uint64_t edge = EDGE;
+        uint64_t tmp;
+        uint32_t inc;
+        asm volatile("s_and_b64 %[tmp], %[e], %[edge]\n\t"
+                     "s_cselect_b32 %[inc], 66, 2\n\t"
+                     "s_add_u32 %[ub], %[ub], %[inc]"
+                     : [tmp] "=&s"(tmp), [inc] "=&s"(inc), [ub] "+s"(ub)
+                     : [e] "s"(e), [edge] "s"(edge)
+                     : "scc");
+        return ub;
+    }
+
+    // this lane's group's candidate slots on the first anti-diagonal of the
+    // half starting dh anti-diagonals after the block start (j <= n: slot >=
+    // d - n - o; i <= m: slot <= m - o); none for an empty group
+    __device__ __forceinline__ static void bounds_at(const GroupX &g0, const GroupX &g1, int dh, int &lo_s,
+                                                     int &hi_s)
+    {
+        const int o0 = g0.base + ((g0.d + dh) >> 1), o1 = g1.base + ((g1.d + dh) >> 1);
+        const int lo0 = g0.t != kNoTask ? g0.d + dh - g0.n - o0 : (1 << 30);
+        const int hi0 = g0.t != kNoTask ? g0.m - o0 : -(1 << 30);
+        const int lo1 = g1.t != kNoTask ? g1.d + dh - g1.n - o1 : (1 << 30);
+        const int hi1 = g1.t != kNoTask ? g1.m - o1 : -(1 << 30);
+        const bool hi = lane_id() >= 32;
+        lo_s = hi ? lo1 : lo0;
+        hi_s = hi ? hi1 : hi0;
+    }
+
+    // Up to np pairs (odd, even anti-diagonal) from dh anti-diagonals after
+    // the block start, ending after the first pair whose even step leaves a
+    // live cell in an edge slot (then ub has 64 added).  Returns ub.
+    template <bool BOUNDS>
+    __device__ __forceinline__ uint32_t pairs(GroupX &g0, GroupX &g1, int dh, int np, int &ti, int &tp, int xv,
+                                              uint32_t sinc0, uint32_t sinc1)
+    {
+        int lo_s = 0, hi_s = 0;
+        if (BOUNDS) bounds_at(g0, g1, dh, lo_s, hi_s);
+        const uint32_t ube = 2u * (uint32_t)np;
+        uint32_t ub = 0;
+        do {
+            step<true, BOUNDS>(g0, g1, ub, ti, tp, xv, lo_s, hi_s, sinc0, sinc1);
+            const uint64_t e = step<false, BOUNDS>(g0, g1, ub, ti, tp, xv, lo_s, hi_s - 1, sinc0, sinc1);
+            if (BOUNDS) {
+                ++lo_s;
+                --hi_s;
+            }
+            ub = next_pair(ub, e);
+        } while (ub < ube);
+        return ub;
+    }
+
+    template <int K = 0>
+    __device__ __forceinline__ uint64_t pairs_spec(GroupX &g0, GroupX &g1, int &ti, int &tp, int xv, uint32_t sinc0,
+                                                   uint32_t sinc1, uint64_t acc)
+    {
+        if constexpr (K == UMAX) {
+            return acc;
+        } else {
+            step<true, false, 2 * K>(g0, g1, 0u, ti, tp, xv, 0, 0, sinc0, sinc1);
+            acc |= step<false, false, 2 * K>(g0, g1, 0u, ti, tp, xv, 0, 0, sinc0, sinc1);
+            return pairs_spec<K + 1>(g0, g1, ti, tp, xv, sinc0, sinc1, acc);
+        }
+    }
+
+    // one half of UMAX pairs at C = 1 without clipping: unrolled with no test
+    // between the pairs, rolled back and rerun with per-pair checks if an
+    // edge slot went live
+    __device__ __forceinline__ uint32_t half_c1(GroupX &g0, GroupX &g1, int dh, int &ti, int &tp, int xv,
+                                                uint32_t sinc0, uint32_t sinc1)
+    {
+        const int z1 = Z1[0], z2 = Z2[0], ti0 = ti, tp0 = tp;
+        const uint32_t li0 = g0.li, li1 = g1.li;
+        const int lu0 = g0.lu, lu1 = g1.lu;
+        const uint64_t c0 = g0.cells, c1 = g1.cells, s0 = g0.slots, s1 = g1.slots;
+        const uint64_t acc = pairs_spec(g0, g1, ti, tp, xv, sinc0, sinc1, 0ull);
+        if (!(acc & EDGE)) return 2u * UMAX;
+        Z1[0] = z1; Z2[0] = z2; ti = ti0; tp = tp0;
+        g0.li = li0; g1.li = li1; g0.lu = lu0; g1.lu = lu1;
+        g0.cells = c0; g1.cells = c1; g0.slots = s0; g1.slots = s1;
+        return pairs<false>(g0, g1, dh, UMAX, ti, tp, xv, sinc0, sinc1);
+    }
+
+    // end cell of group g's last improvement in the half that began at its
+    // anti-diagonal d0
+    __device__ __forceinline__ void resolve(GroupX &g, int gi, int d0) const
+    {
+        if (g.lu < 0) return;
+        const int dd = d0 + g.lu;
+        const int l = __builtin_ctz(g.li);
+        int slot = C * l;
+        if (C > 1) slot += __builtin_amdgcn_readlane(rs, 32 * gi + l);
+        g.bi = g.base + (dd >> 1) + slot;
+        g.bj = dd - g.bi;
+        g.lu = -1;
+    }
+};
+
+// Queue of the narrow class, as seen by one wavefront.
+struct NarrowQueue {
+    uint32_t cnt;     // tasks in the queue
+    bool drained;     // a fetch came back empty
+};
+
+// Ends group g's extension: result written, lanes dead, threshold reset
+// (so that its drop threshold stays far above the dead value)
+template <int C, bool COUNT>
+__device__ __forceinline__ void narrow_end(const BatchDev &b, PairWin<C, COUNT> &w, GroupX &g, int gi, int &ti)
+{
+    const int T = __builtin_amdgcn_readlane(ti, 32 * gi) - g.d;
+    TaskOut o;
+    o.score = T; o.i = g.bi; o.j = g.bj; o.status = (uint32_t)kNarrowClass; o.cells = g.cells; o.slots = g.slots;
+    b.tout[g.t] = o;
+    g.t = kNoTask;
+    w.set_group(gi, false);
+    ti = ((lane_id() >> 5) == gi) ? 0 : ti;
+}
+
+// Starts task t in group g: fresh window lanes, threshold of anti-diagonal 1
+template <int C, bool COUNT>
+__device__ __forceinline__ void narrow_start(const BatchDev &b, const StoreDev &st, PairWin<C, COUNT> &w, GroupX &g,
+                                             int gi, uint32_t t, int &ti)
+{
+    const Task k = load_task(b.recs, st.reads, t);
+    g.t = t;
+    g.d = 1;
+    g.base = -(PairWin<C, COUNT>::WIN / 2 - 1);
+    g.bi = 0; g.bj = 0;
+    g.m = k.g.m; g.n = k.g.n; g.x = k.x;
+    g.sx = k.mi + 2;
+    g.abase = k.g.abase; g.bbase = k.g.bbase;
+    g.cells = 0; g.slots = 0;
+    g.li = 0; g.lu = -1;
+    g.mn = g.mx = PairWin<C, COUNT>::WIN / 2 - 1;
+    w.set_group(gi, true);
+    ti = ((lane_id() >> 5) == gi) ? 1 : ti;   // T = 0, plus d = 1 (Z units, gap 1)
+}
+
+// Runs blocks until both groups are empty and the queue is drained (kDone),
+// or until the window must change width (kGrow / kShrink, the window saved
+// to LDS and each group's mn / mx set).  shrink_width < 0: never narrow.
+template <int C, bool COUNT>
+__device__ uint32_t narrow_run(const BatchDev &b, const StoreDev &st, PairWin<C, COUNT> &w, GroupX &g0, GroupX &g1,
+                               int &ti, int *lds, NarrowQueue &q, int shrink_width)
+{
+    using PW = PairWin<C, COUNT>;
+    constexpr int WIN = PW::WIN;
+    const uint32_t *__restrict__ W = st.words;
+    const uint32_t qcap = 2u * b.cap;
+    const int lane = lane_id();
+    const bool hi = lane >= 32;
+    const int gl = lane & 31;
+    for (;;) {
+        w.bands(g0, g1);
+        // extensions that ended: two dead anti-diagonals, or past the far corner
+        if (g0.t != kNoTask && (g0.mx < 0 || g0.d > g0.m + g0.n)) narrow_end(b, w, g0, 0, ti);
+        if (g1.t != kNoTask && (g1.mx < 0 || g1.d > g1.m + g1.n)) narrow_end(b, w, g1, 1, ti);
+        // empty groups take the next tasks
+        if (!q.drained && (g0.t == kNoTask || g1.t == kNoTask)) {
+            const uint32_t k = (g0.t == kNoTask ? 1u : 0u) + (g1.t == kNoTask ? 1u : 0u);
+            uint32_t idx = wave_fetch_add(&b.ctr[CtrLayout::kHead + kNarrowClass], k);
+            if (g0.t == kNoTask) {
+                if (idx < q.cnt) narrow_start(b, st, w, g0, 0, (uint32_t)uni((int)b.qbuf[kNarrowClass * qcap + idx]), ti);
+                ++idx;
+            }
+            if (g1.t == kNoTask && idx < q.cnt)
+                narrow_start(b, st, w, g1, 1, (uint32_t)uni((int)b.qbuf[kNarrowClass * qcap + idx]), ti);
+            if (idx >= q.cnt) q.drained = true;
+        }
+        const bool e0 = g0.t == kNoTask, e1 = g1.t == kNoTask;
+        if (e0 && e1) return kDone;
+        const int w0 = e0 ? 0 : g0.mx - g0.mn + 1;
+        const int w1 = e1 ? 0 : g1.mx - g1.mn + 1;
+        if (w0 + 4 > WIN || w1 + 4 > WIN) {
+            if (C == 1) {
+                w.save(lds);
+                return kGrow;
+            }
+            // wider than the widest window: the task restarts in the adaptive class
+            for (int gi = 0; gi < 2; ++gi) {
+                GroupX &g = gi ? g1 : g0;
+                if ((gi ? w1 : w0) + 4 <= WIN) continue;
+                const uint32_t pos = wave_fetch_add(&b.ctr[CtrLayout::kCount + kAdaptiveClass], 1u);
+                b.qbuf[kAdaptiveClass * qcap + pos] = g.t;
+                g.t = kNoTask;
+                w.set_group(gi, false);
+                ti = ((lane >> 5) == gi) ? 0 : ti;
+            }
+            continue;
+        }
+        if (w0 <= shrink_width && w1 <= shrink_width) {
+            w.save(lds);
+            return kShrink;
+        }
+        // re-centre a band that starts closer than kRecentre slots to an edge
+        const int dl0 = (!e0 && min(g0.mn, WIN - 1 - g0.mx) < kRecentre) ? g0.mn - (WIN - w0) / 2 : 0;
+        const int dl1 = (!e1 && min(g1.mn, WIN - 1 - g1.mx) < kRecentre) ? g1.mn - (WIN - w1) / 2 : 0;
+        if (dl0 | dl1) {
+            w.save(lds);
+            w.load(lds, WIN, hi ? dl1 : dl0);
+            g0.base += dl0;
+            g1.base += dl1;
+        }
+        // pairs up to each group's far corner; the block runs the longer and
+        // clips the other
+        const int P0 = e0 ? 0 : min(PW::PB, (g0.m + g0.n - g0.d + 2) >> 1);
+        const int P1 = e1 ? 0 : min(PW::PB, (g1.m + g1.n - g1.d + 2) >> 1);
+        const int P = max(P0, P1);
+        // no clipping when every slot that can hold a candidate (0 .. WIN-2)
+        // of every anti-diagonal of the block lies inside the group's table
+        auto clear_of_ends = [&](const GroupX &g, bool e) {
+            if (e) return true;
+            const int dlast = g.d + 2 * P - 1;
+            const int o_last = g.base + (dlast >> 1);
+            return o_last + WIN - 2 <= g.m && o_last >= dlast - g.n;
+        };
+        const bool fast = clear_of_ends(g0, e0) && clear_of_ends(g1, e1);
+        // codes of this lane's group (an empty group reads the other's, which
+        // keeps its loads inside the store; its cells are dead)
+        const GroupX &ga = e0 ? g1 : g0;
+        const GroupX &gb = e1 ? g0 : g1;
+        const uint64_t abase = hi ? gb.abase : ga.abase, bbase = hi ? gb.bbase : ga.bbase;
+        const int dsel = hi ? gb.d : ga.d, bsel = hi ? gb.base : ga.base;
+        const int sx = hi ? gb.sx : ga.sx;
+        const int xv = hi ? g1.x : g0.x;
+        {
+            const uint32_t *aseq = W + (abase >> 4), *bseq = W + (bbase >> 4);
+            const int aph = (int)(abase & 15), bph = (int)(bbase & 15);
+            const int e0d = (dsel - 1) >> 1;
+            const int A0 = bsel + e0d - 1, B0 = e0d - bsel;
+            uint32_t aw[PW::NWC], bw[PW::NWC];
+            load_codes<PW::NWC>(aseq, aph, A0 + C * gl, aw);
+            load_codes<PW::NWC>(bseq, bph, B0 - C * gl - (C - 1), bw);
+            const uint32_t base_f = (uint32_t)kNarrowSm * 0x55555555u;
+            const uint32_t kx = (uint32_t)(kNarrowSm ^ sx);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int r = 0; r < C; ++r) {
+                    const uint32_t bb = codes16<PW::NWC>(bw, C - 1 - r + 16 * h);
+                    const uint32_t xo = codes16<PW::NWC>(aw, r + 16 * h) ^ bb;
+                    const uint32_t xe = codes16<PW::NWC>(aw, r + 1 + 16 * h) ^ bb;
+                    const uint32_t mo = (xo | (xo >> 1)) & 0x55555555u;   // 1 = mismatch, at bit 2u
+                    const uint32_t me = (xe | (xe >> 1)) & 0x55555555u;
+                    // field u = sigma'' of pair u: sm ^ (mismatch ? sm ^ sx : 0)
+                    const uint32_t fo = base_f ^ ((kx & 1u) ? mo : 0u) ^ ((kx & 2u) ? (mo << 1) : 0u);
+                    const uint32_t fe = base_f ^ ((kx & 1u) ? me : 0u) ^ ((kx & 2u) ? (me << 1) : 0u);
+                    if (h == 0) { w.mmo[r] = fo; w.mme[r] = fe; }
+                    else { w.mmo2[r] = fo; w.mme2[r] = fe; }
+                }
+            }
+        }
+        // slot-steps charged to each group (an empty group's lanes to the other)
+        const uint32_t sinc0 = e0 ? 0u : (e1 ? 2u * WIN : (uint32_t)WIN);
+        const uint32_t sinc1 = e1 ? 0u : (e0 ? 2u * WIN : (uint32_t)WIN);
+        int tp = ti - xv;
+        const int p0 = min(P, UMAX);
+        uint32_t ub;
+        if (C == 1 && fast && p0 == UMAX)
+            ub = w.half_c1(g0, g1, 0, ti, tp, xv, sinc0, sinc1);
+        else if (fast)
+            ub = w.template pairs<false>(g0, g1, 0, p0, ti, tp, xv, sinc0, sinc1);
+        else
+            ub = w.template pairs<true>(g0, g1, 0, p0, ti, tp, xv, sinc0, sinc1);
+        int u = (int)(ub & 63u) >> 1;
+        if (ub < 64u && P > UMAX && w.alive()) {
+            w.resolve(g0, 0, g0.d);
+            w.resolve(g1, 1, g1.d);
+#pragma unroll
+            for (int r = 0; r < C; ++r) {
+                w.mmo[r] = w.mmo2[r];
+                w.mme[r] = w.mme2[r];
+            }
+            if (C == 1 && fast && P == PW::PB)
+                ub = w.half_c1(g0, g1, 2 * UMAX, ti, tp, xv, sinc0, sinc1);
+            else if (fast)
+                ub = w.template pairs<false>(g0, g1, 2 * UMAX, P - UMAX, ti, tp, xv, sinc0, sinc1);
+            else
+                ub = w.template pairs<true>(g0, g1, 2 * UMAX, P - UMAX, ti, tp, xv, sinc0, sinc1);
+            u = UMAX + ((int)(ub & 63u) >> 1);
+            w.resolve(g0, 0, g0.d + 2 * UMAX);
+            w.resolve(g1, 1, g1.d + 2 * UMAX);
+        } else {
+            w.resolve(g0, 0, g0.d);
+            w.resolve(g1, 1, g1.d);
+        }
+        if (!e0) g0.d += 2 * u;
+        if (!e1) g1.d += 2 * u;
+    }
+}
+
+// Class 0: narrow bands, two extensions per wavefront (weights match 1, gap
+// -1, mismatch 0 / -1 / -2 and drops up to the narrow_x knob; the ingest
+// kernel queues only those).  Each wavefront drains the queue two tasks at a
+// time until it is empty; a band wider than 64 slots sends its task to the
+// adaptive class.
+template <bool COUNT>
+__global__ void __launch_bounds__(256) narrow_kernel(BatchDev b, StoreDev st, int shrink_margin)
+{
+    __shared__ int lds_all[4][2 * PairWin<2, COUNT>::STRIDE];
+    int *lds = lds_all[threadIdx.x >> 6];
+    NarrowQueue q;
+    q.cnt = b.ctr[CtrLayout::kCount + kNarrowClass];
+    q.drained = false;
+    GroupX g0{}, g1{};
+    g0.t = g1.t = kNoTask;
+    g0.lu = g1.lu = -1;
+    int ti = 0;
+    // back to 32 slots once every band fits them with shrink_margin to spare
+    const int shrink2 = 32 - 2 * max(shrink_margin, 2);
+    int C = 1, from_win = 0, dl = 0;
+    bool fresh = true;
+    for (;;) {
+        uint32_t r;
+        if (C == 1) {
+            PairWin<1, COUNT> w;
+            if (fresh) w.clear(); else w.load(lds, from_win, dl);
+            r = narrow_run(b, st, w, g0, g1, ti, lds, q, -1);
+        } else {
+            PairWin<2, COUNT> w;
+            w.load(lds, from_win, dl);
+            r = narrow_run(b, st, w, g0, g1, ti, lds, q, shrink2);
+        }
+        if (r == kDone) break;
+        fresh = false;
+        const int nc = r == kGrow ? 2 : 1;
+        from_win = 32 * C;
+        int dl0 = 0, dl1 = 0;
+        if (g0.t != kNoTask) {
+            dl0 = g0.mn - (32 * nc - (g0.mx - g0.mn + 1)) / 2;
+            g0.base += dl0;
+        }
+        if (g1.t != kNoTask) {
+            dl1 = g1.mn - (32 * nc - (g1.mx - g1.mn + 1)) / 2;
+            g1.base += dl1;
+        }
+        dl = lane_id() >= 32 ? dl1 : dl0;
+        C = nc;
+    }
+}
+
+// Class 1: adaptive windows.  Tasks whose band outgrows 256 cells go to the
+// first wide class.  Registers capped for 6 wavefronts per SIMD (the
+// compiler's own choice allows 5; the cap costs one spill at entry and its
+// reload per task).
 template <bool COUNT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) adaptive_kernel(BatchDev b, StoreDev st, int grow_margin, int shrink_margin)
 {
     __shared__ int lds_all[4][2 * WMAX];
     int *lds = lds_all[threadIdx.x >> 6];
-    const int cls = 0;
+    const int cls = kAdaptiveClass;
     const uint32_t qcap = 2u * b.cap;
     const uint32_t cnt = b.ctr[CtrLayout::kCount + cls];
     for (;;) {
@@ -1498,6 +2089,16 @@ void launch_bucket(const BatchDev &b, const StoreDev &st, uint32_t n, hipStream_
     if (blocks) hipLaunchKernelGGL(bucket_scatter_kernel, dim3(blocks), dim3(256), 0, s, b, st);
 }
 
+void launch_narrow(const BatchDev &b, const StoreDev &st, const Tuning &tu, uint32_t grid_waves, bool count_cells,
+                   hipStream_t s)
+{
+    const uint32_t blocks = (grid_waves + 3) / 4;
+    if (count_cells)
+        hipLaunchKernelGGL(narrow_kernel<true>, dim3(blocks), dim3(256), 0, s, b, st, tu.shrink_margin);
+    else
+        hipLaunchKernelGGL(narrow_kernel<false>, dim3(blocks), dim3(256), 0, s, b, st, tu.shrink_margin);
+}
+
 void launch_adaptive(const BatchDev &b, const StoreDev &st, const Tuning &tu, uint32_t grid_waves, bool count_cells,
                      hipStream_t s)
 {
@@ -1524,8 +2125,8 @@ void launch_wide(int which, const BatchDev &b, const StoreDev &st, uint32_t grid
                  hipStream_t s)
 {
     static_assert(kWideClasses == 2, "wide classes");
-    if (which == 0) launch_wide_c<0>(b, st, 1 + which, grid_waves, count_cells, s);
-    else launch_wide_c<1>(b, st, 1 + which, grid_waves, count_cells, s);
+    if (which == 0) launch_wide_c<0>(b, st, kAdaptiveClass + 1 + which, grid_waves, count_cells, s);
+    else launch_wide_c<1>(b, st, kAdaptiveClass + 1 + which, grid_waves, count_cells, s);
 }
 
 void launch_generic(const BatchDev &b, const StoreDev &st, int32_t *scratch, uint64_t stride, uint32_t blocks,

@@ -43,8 +43,8 @@ class Config(ctypes.Structure):
                 ("tuning_cache", ctypes.c_char_p), ("flags", ctypes.c_uint32)]
 
 
-NUM_STAGES = 6
-STAGE_NAMES = ("ingest", "adaptive", "wide1024", "wide2048", "generic", "finalize")
+NUM_STAGES = 7
+STAGE_NAMES = ("ingest", "narrow", "adaptive", "wide1024", "wide2048", "generic", "finalize")
 FLAG_PROFILE = 1
 
 
@@ -79,7 +79,7 @@ class SeedStats(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("grow_margin", ctypes.c_int32), ("shrink_margin", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("buckets", ctypes.c_int32),
-                ("generic_waves", ctypes.c_int32)]
+                ("generic_waves", ctypes.c_int32), ("narrow_x", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

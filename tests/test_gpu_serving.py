@@ -122,7 +122,8 @@ def test_wide_bands_alone_equals_mixed(xd):
         for b in batches:
             res, cells, st = ctx.run(b, count_cells=True)
             alone.append((res, cells))
-            wide_tasks += int(st["stage_tasks"][3]) + int(st["stage_tasks"][4])
+            wide_tasks += int(st["stage_tasks"][xd.STAGE_NAMES.index("wide2048")]) + \
+                int(st["stage_tasks"][xd.STAGE_NAMES.index("generic")])
     assert wide_tasks > 0   # extensions finished after a hand-over
     note("wide bands mixed: 6 producer threads, 4 slots in flight")
     mixed = [None] * len(batches)
