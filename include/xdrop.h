@@ -137,11 +137,13 @@ typedef struct {
     double total_ms;              /* submit entry -> completion             */
     double stage_ms[XDROP_NUM_STAGES];      /* XDROP_FLAG_PROFILE only; summed over
                                                chunks in the plain form    */
-    uint64_t stage_cells[XDROP_NUM_STAGES]; /* cells of the extensions each stage
-                                               completed (cell counting, persistent
-                                               form only)                  */
+    uint64_t stage_cells[XDROP_NUM_STAGES]; /* cells each stage computed for the
+                                               extensions it completed or handed
+                                               over with their state (cell counting,
+                                               persistent form only); work lost to a
+                                               restart is not counted      */
     uint64_t stage_tasks[XDROP_NUM_STAGES]; /* extensions each stage completed (idem) */
-    uint64_t stage_slots[XDROP_NUM_STAGES]; /* window lane-steps those extensions took
+    uint64_t stage_slots[XDROP_NUM_STAGES]; /* window lane-steps of the same work
                                                (idem); stage_cells / stage_slots is
                                                the lane occupancy of the stage     */
 } xdrop_batch_stats;

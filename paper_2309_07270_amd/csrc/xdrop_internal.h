@@ -72,7 +72,8 @@ struct BatchDev {
     uint32_t carry_words;     // capacity of carry, in words
     uint32_t *ctr;            // counters, see CtrLayout
     uint32_t *bucket_hist;    // kNumClasses * kNumBuckets
-    unsigned long long *stage_sum;  // kStageSumWords: [0..7] cells, [8..15] tasks, [16..23] slot-steps per stage (1 + class)
+    unsigned long long *stage_sum;  // kStageSumWords: [0..7] cells, [8..15] tasks completed, [16..23] slot-steps
+                                    // per stage (1 + class); cells and slot-steps count the work each stage did
     uint32_t cap;             // record capacity of the buffers
 };
 

@@ -1713,6 +1713,18 @@ wide_kernel(BatchDev b, StoreDev st, int cls)
             const uint32_t pos = wave_fetch_add(&b.ctr[CtrLayout::kCount + cls + 1], 1u);
             b.qbuf[(cls + 1) * qcap + pos] = t;
             b.qstate[(cls + 1) * qcap + pos] = out_off;
+            if (COUNT && out_off != kNoCarry && lane_id() == 0) {
+                // the carried state keeps the task's running cell and
+                // slot-step totals, which the class that completes it
+                // reports: credit this class with what it computed so far
+                // and debit the next one the same (modulo 2^64), so that
+                // each stage's sums hold only its own work
+                const int stg = 1 + cls;
+                atomicAdd(&b.stage_sum[stg], (unsigned long long)s.cells);
+                atomicAdd(&b.stage_sum[stg + 1], 0ull - (unsigned long long)s.cells);
+                atomicAdd(&b.stage_sum[16 + stg], (unsigned long long)s.slots);
+                atomicAdd(&b.stage_sum[16 + stg + 1], 0ull - (unsigned long long)s.slots);
+            }
         }
     }
 }

@@ -243,6 +243,14 @@ def test_bands_widen_then_narrow(xd, weights):
     assert_same(res, cells, ref)
     tasks = [int(v) for v in st["stage_tasks"][1:6]]
     assert tasks == want, (tasks, want)
+    # each stage reports the cells it computed, also for extensions it
+    # handed to a wider class: the sums add up to the per-record counts,
+    # every window stage holds at least its cells in lane-steps, and every
+    # class that ran reports work
+    sc = np.array(st["stage_cells"], np.uint64)
+    ss = np.array(st["stage_slots"], np.uint64)
+    assert int(sc.sum()) == int(cells.sum())
+    assert np.all(ss >= sc) and np.all(sc[2:6] > 0), (sc, ss)
 
 
 def test_identical_reads_full_length(xd):
