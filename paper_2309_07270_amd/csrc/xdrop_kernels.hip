@@ -1948,6 +1948,13 @@ __device__ void generic_start(const BatchDev &b, uint32_t coff, int gap, int *P1
     s.slots = (uint64_t)(uint32_t)rec[CarryLayout::kSlots] | ((uint64_t)(uint32_t)rec[CarryLayout::kSlots + 1] << 32);
     const int base = rec[CarryLayout::kBase], win = rec[CarryLayout::kWin];
     if (tid == 0) { s_rng[0] = 0x7fffffff; s_rng[1] = -1; s_rng[2] = 0x7fffffff; s_rng[3] = -1; }
+    // Every slot of the two rings starts dead: the anti-diagonals read any
+    // slot between the live ends, and a carried band has dead cells inside
+    // it, which would otherwise keep what an earlier task left in the ring.
+    for (int q = tid; q < kRing; q += kGenericThreads) {
+        P1[q] = NEG;
+        P2[q] = NEG;
+    }
     __syncthreads();
     const int G = -gap, d1 = s.d - 1, d2 = s.d - 2;
     const int o1 = base + (d1 >> 1), o2 = base + (d2 >> 1);   // i of slot 0 (d2 >= 0: a window ran)

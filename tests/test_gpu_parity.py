@@ -141,6 +141,25 @@ def test_unbounded_band_wider_than_lds_ring(xd):
     assert_same(res, cells, ref)
 
 
+def test_unbounded_resume_into_used_ring(xd):
+    # Unrelated 6-9 kb reads at X = 600-900 (+1/-1/-1): bands of 1,700-2,900
+    # ragged cells climb through both wide classes with their state and
+    # resume in the unbounded kernel.  One workgroup (generic_waves 16) runs
+    # those extensions one after another, so every resumed band lands in a
+    # ring that holds the previous extension's values; the dead cells inside
+    # a carried band must read as dead there.
+    rng = np.random.Generator(np.random.PCG64(91))
+    store = W.random_store(rng, 24, 6000, 9000, related=0.0)
+    recs = W.random_records(rng, store, 40, x_choices=(600, 900), k_max=5, weights=((1, -1, -1),))
+    ref, _ = oracle.batch(store.codes, store.off, store.length, recs)
+    note("unbounded kernel: carried ragged bands resumed in a used ring (one workgroup)")
+    with xd.Context(store) as ctx:
+        ctx.set_tuning(generic_waves=16)
+        res, cells, st = ctx.run(recs, count_cells=True)
+    assert int(st["stage_tasks"][xd.STAGE_NAMES.index("generic")]) >= 4
+    assert_same(res, cells, ref)
+
+
 def test_class_hand_over_pool_overflow(xd):
     # Every right extension here outgrows the 1024- and 2048-slot windows
     # (X = 2^30, ~2.3 kb on both sides), so each record hands about 6,200
