@@ -142,17 +142,29 @@ def test_unbounded_band_wider_than_lds_ring(xd):
 
 
 def test_unbounded_resume_into_used_ring(xd):
-    # Unrelated 6-9 kb reads at X = 600-900 (+1/-1/-1): bands of 1,700-2,900
-    # ragged cells climb through both wide classes with their state and
-    # resume in the unbounded kernel.  One workgroup (generic_waves 16) runs
-    # those extensions one after another, so every resumed band lands in a
-    # ring that holds the previous extension's values; the dead cells inside
-    # a carried band must read as dead there.
-    rng = np.random.Generator(np.random.PCG64(91))
-    store = W.random_store(rng, 24, 6000, 9000, related=0.0)
-    recs = W.random_records(rng, store, 40, x_choices=(600, 900), k_max=5, weights=((1, -1, -1),))
+    # Unrelated 70-95 kb reads at X = 100 (+1/-1/-1), seeds near the start:
+    # the right extensions run the whole reads with ragged bands of 2,200-
+    # 3,100 cells (dead cells inside the band), climb through both wide
+    # classes with their state and resume in the unbounded kernel.  One
+    # workgroup (generic_waves 16) runs those extensions one after another,
+    # so every resumed band lands in a ring that holds the previous
+    # extension's values; the dead cells inside a carried band must read as
+    # dead there (the stress mix's long unrelated pairs hit this).
+    rng = np.random.Generator(np.random.PCG64(92))
+    lens = rng.integers(70000, 95001, size=12)
+    codes = rng.integers(0, 4, int(lens.sum())).astype(np.uint8)
+    store = W.ReadStore(codes, np.concatenate([[0], np.cumsum(lens)[:-1]]), lens)
+    n = 8
+    recs = np.zeros(n, W.RECORD_DTYPE)
+    recs["read_a"] = np.arange(n)
+    recs["read_b"] = (np.arange(n) + 1 + rng.integers(0, 11, n)) % 12
+    recs["pos_a"] = rng.integers(0, 50, n)
+    recs["pos_b"] = rng.integers(0, 50, n)
+    recs["k"] = 3
+    recs["x"] = 100
+    recs["match"], recs["mismatch"], recs["gap"] = 1, -1, -1
     ref, _ = oracle.batch(store.codes, store.off, store.length, recs)
-    note("unbounded kernel: carried ragged bands resumed in a used ring (one workgroup)")
+    note("unbounded kernel: carried ragged bands resumed in a used ring (one workgroup, 70-95 kb, X = 100)")
     with xd.Context(store) as ctx:
         ctx.set_tuning(generic_waves=16)
         res, cells, st = ctx.run(recs, count_cells=True)
