@@ -92,7 +92,7 @@ enum {
                                      32 or 64 slots over half the lanes     */
     XDROP_STAGE_ADAPTIVE = 2,     /* register window of 64..256 slots that
                                      follows the band width                 */
-    XDROP_STAGE_WIDE1024 = 3,     /* register window of 512..1024 slots that
+    XDROP_STAGE_WIDE1280 = 3,     /* register window of 512..1280 slots that
                                      follows the band width                 */
     XDROP_STAGE_WIDE2048 = 4,     /* register window of 1536..2048 slots    */
     XDROP_STAGE_GENERIC = 5,      /* unbounded band: one workgroup per

@@ -36,15 +36,15 @@ struct TaskOut {
 //      window of 32 or 64 slots over one half of the lanes;
 //   1  adaptive register window, 1..4 cells per lane (64..256 slots), the
 //      width following the band;
-//   2  register window of 8, 12 or 16 cells per lane (512..1024 slots), the
-//      width following the band;
+//   2  register window of 8, 12, 16 or 20 cells per lane (512..1280 slots),
+//      the width following the band;
 //   3  register window of 24 or 32 cells per lane (1536..2048 slots);
 //   4  unbounded band: one workgroup per extension, anti-diagonals in an LDS
 //      ring (global memory beyond 8192 cells).
 constexpr int kNarrowClass = 0;
 constexpr int kAdaptiveClass = 1;
 constexpr int kWideClasses = 2;
-constexpr int kWideC[kWideClasses] = {16, 32};   // widest window of each wide class, cells per lane
+constexpr int kWideC[kWideClasses] = {20, 32};   // widest window of each wide class, cells per lane
 constexpr int kGenericClass = kAdaptiveClass + 1 + kWideClasses;
 constexpr int kNumClasses = kGenericClass + 1;
 constexpr int kNumStages = kNumClasses + 2;   // ingest, classes..., finalize

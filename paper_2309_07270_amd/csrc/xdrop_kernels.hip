@@ -1578,21 +1578,21 @@ __device__ __forceinline__ void carry_state(const int32_t *rec, XState &s)
 // the class limit (kWideC).
 template <int L> struct WideLadder;
 template <> struct WideLadder<0> {
-    static constexpr int N = 3;
-    static constexpr int C0 = 8, C1 = 12, C2 = 16;
+    static constexpr int N = 4;
+    static constexpr int C0 = 8, C1 = 12, C2 = 16, C3 = 20;
 };
 template <> struct WideLadder<1> {
     static constexpr int N = 2;
-    static constexpr int C0 = 24, C1 = 32, C2 = 32;
+    static constexpr int C0 = 24, C1 = 32, C2 = 32, C3 = 32;
 };
-static_assert(WideLadder<0>::C2 == kWideC[0] && WideLadder<1>::C1 == kWideC[1], "class limits");
+static_assert(WideLadder<0>::C3 == kWideC[0] && WideLadder<1>::C1 == kWideC[1], "class limits");
 constexpr int kWideGrowMargin = 32;     // free slots per side after widening
 constexpr int kWideShrinkMargin = 64;   // narrow once the band fits the next smaller window with this slack
 
 template <int L>
 __device__ __forceinline__ int ladder_c(int ci)
 {
-    return ci == 0 ? WideLadder<L>::C0 : ci == 1 ? WideLadder<L>::C1 : WideLadder<L>::C2;
+    return ci == 0 ? WideLadder<L>::C0 : ci == 1 ? WideLadder<L>::C1 : ci == 2 ? WideLadder<L>::C2 : WideLadder<L>::C3;
 }
 
 // smallest rung whose window holds `width` slots with `margin` free on each side; -1 if none
@@ -1649,9 +1649,15 @@ __device__ uint32_t run_ladder(const BatchDev &b, const StoreDev &st, const Task
             Window<LD::C1, COUNT, MA1, SIGF, STRIDE> w;
             w.load(lds, from_win, delta);
             stt = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
-        } else {
+        } else if (LD::N == 3 || ci == 2) {
             if constexpr (LD::N > 2) {
                 Window<LD::C2, COUNT, MA1, SIGF, STRIDE> w;
+                w.load(lds, from_win, delta);
+                stt = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
+            }
+        } else {
+            if constexpr (LD::N > 3) {
+                Window<LD::C3, COUNT, MA1, SIGF, STRIDE> w;
                 w.load(lds, from_win, delta);
                 stt = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
             }
@@ -1680,8 +1686,10 @@ __device__ uint32_t run_ladder(const BatchDev &b, const StoreDev &st, const Task
 }
 
 // Wide class L for bands the adaptive kernel cannot hold.  The first class
-// (up to 1024 slots) runs 2 wavefronts per SIMD (256 VGPRs, no spills); the
-// second (up to 2048 slots) needs the whole register file.
+// (up to 1280 slots) runs 2 wavefronts per SIMD (256 VGPRs; the 1280-slot
+// rung costs a few spills at task entry); the second (up to 2048 slots)
+// needs the whole register file and runs 1 per SIMD, so bands up to 1276
+// cells stay in the first.
 template <int L, bool COUNT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(L == 0 ? 2 : 1)))
 wide_kernel(BatchDev b, StoreDev st, int cls)

@@ -44,7 +44,7 @@ class Config(ctypes.Structure):
 
 
 NUM_STAGES = 7
-STAGE_NAMES = ("ingest", "narrow", "adaptive", "wide1024", "wide2048", "generic", "finalize")
+STAGE_NAMES = ("ingest", "narrow", "adaptive", "wide1280", "wide2048", "generic", "finalize")
 FLAG_PROFILE = 1
 
 

@@ -209,11 +209,11 @@ def test_class_hand_over_pool_overflow(xd):
 
 # Window classes by the widest live range of an extension (from the oracle):
 # the adaptive windows hold bands up to 252 slots, the first wide class up to
-# 1020, the second up to 2044; wider bands finish in the unbounded kernel.
+# 1276, the second up to 2044; wider bands finish in the unbounded kernel.
 # Each case below sits at least 6 % away from those limits.  Extensions of
 # small drops with match 1, gap -1 (narrow class, two per wavefront) stay
 # there while their band fits 60 slots.
-CLASS_BRACKETS = ((0, 235), (275, 955), (1090, 1915), (2175, 1 << 30))
+CLASS_BRACKETS = ((0, 235), (275, 1195), (1360, 1915), (2175, 1 << 30))
 NARROW_LIMIT = (56, 64)   # a narrow-class band at most the first completes there; none in between
 NARROW_X = 20             # default drop bound of the narrow class
 
@@ -223,9 +223,9 @@ def narrow_eligible(weights, x):
     return x <= NARROW_X and ma == 1 and gap == -1 and mi >= -2
 WIDEN_NARROW_CASES = {
     # weights: (read a, read b, X) per record, one or two records per class
-    (1, -1, -1): [(2, 1, 14), (0, 2, 25), (2, 3, 30), (2, 3, 300), (0, 1, 400), (2, 3, 1200), (0, 1, 1500)],
+    (1, -1, -1): [(2, 1, 14), (0, 2, 25), (2, 3, 30), (2, 3, 300), (0, 1, 600), (2, 3, 1200), (0, 1, 1500)],
     (1, -2, -2): [(0, 1, 190), (0, 1, 400), (0, 1, 500), (0, 1, 2000), (0, 1, 2500), (0, 1, 4000)],
-    (2, -3, -2): [(0, 2, 36), (1, 3, 50), (0, 1, 60), (2, 3, 500), (0, 1, 600), (2, 3, 2000), (0, 1, 2400)],
+    (2, -3, -2): [(0, 2, 36), (1, 3, 50), (0, 1, 60), (2, 3, 500), (0, 1, 1100), (2, 3, 2000), (0, 1, 2400)],
 }
 
 
@@ -252,7 +252,7 @@ def test_bands_widen_then_narrow(xd, weights):
     recs["k"] = 1
     recs["x"] = [c[2] for c in cases]
     recs["match"], recs["mismatch"], recs["gap"] = weights
-    want = [0] * 5           # narrow, adaptive, 1024-slot, 2048-slot, unbounded
+    want = [0] * 5           # narrow, adaptive, 1280-slot, 2048-slot, unbounded
     for a, b, x in cases:
         _, width = oracle.extend_band(reads[a][1:], reads[b][1:], *weights, x)
         cls = [k for k, (lo, hi) in enumerate(CLASS_BRACKETS) if lo <= width <= hi]
