@@ -195,6 +195,9 @@ typedef struct {
     int32_t narrow_x;             /* persistent form: records with x <= narrow_x and weights
                                      match 1, gap -1, mismatch 0 / -1 / -2 run two extensions
                                      per wavefront (narrow stage); -1: off; at most 64        */
+    int32_t narrow_min_records;   /* ... only in batches of at least this many records (>= 0):
+                                     a smaller batch has too few such extensions to hide the
+                                     narrow stage's tail                                      */
 } xdrop_tuning;
 
 /* Current launch parameters of a context. */

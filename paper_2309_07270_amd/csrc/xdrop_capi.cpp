@@ -185,6 +185,10 @@ Tuning default_tuning()
     // holds a 96 KB LDS ring); fewer when their scratch would pass 256 MiB
     t.generic_waves = 256 * kGenericBlockWaves;
     t.narrow_x = 20;
+    // a smaller batch holds too few narrow extensions to hide the narrow
+    // stage's tail (its longest extension), which then adds to the adaptive
+    // stage's own: one wavefront per extension finishes such a batch sooner
+    t.narrow_min = 100000;
     return t;
 }
 
@@ -206,6 +210,8 @@ bool load_tuning(const std::string &path, Tuning &t)
             f >> t.generic_waves;
         } else if (key == "narrow_x") {
             f >> t.narrow_x;
+        } else if (key == "narrow_min_records") {
+            f >> t.narrow_min;
         } else {
             std::string rest;
             std::getline(f, rest);
@@ -711,6 +717,7 @@ void clamp_tuning(Tuning &t)
     t.generic_waves = (std::min(std::max(t.generic_waves, kGenericBlockWaves), 4096) + kGenericBlockWaves - 1) /
                       kGenericBlockWaves * kGenericBlockWaves;
     t.narrow_x = std::min(std::max(t.narrow_x, -1), kNarrowMaxX);
+    t.narrow_min = std::max(t.narrow_min, 0);
 }
 
 // new launch parameters: captured graphs hold the old ones; the unbounded
@@ -846,7 +853,8 @@ bool write_tuning(const std::string &path, const Tuning &t)
       << "waves_per_cu " << t.waves_per_cu << "\n"
       << "buckets " << t.buckets << "\n"
       << "generic_waves " << t.generic_waves << "\n"
-      << "narrow_x " << t.narrow_x << "\n";
+      << "narrow_x " << t.narrow_x << "\n"
+      << "narrow_min_records " << t.narrow_min << "\n";
     return (bool)f;
 }
 
@@ -1066,6 +1074,7 @@ xdrop_status xdrop_get_tuning(const xdrop_ctx *c, xdrop_tuning *out)
     out->buckets = c->tune.buckets;
     out->generic_waves = c->tune.generic_waves;
     out->narrow_x = c->tune.narrow_x;
+    out->narrow_min_records = c->tune.narrow_min;
     return XDROP_OK;
 }
 
@@ -1081,6 +1090,7 @@ xdrop_status xdrop_set_tuning(xdrop_ctx *c, const xdrop_tuning *in)
     t.buckets = in->buckets;
     t.generic_waves = in->generic_waves;
     t.narrow_x = in->narrow_x;
+    t.narrow_min = in->narrow_min_records;
     clamp_tuning(t);
     try {
         apply_tuning(c, t);

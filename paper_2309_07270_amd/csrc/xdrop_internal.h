@@ -122,6 +122,7 @@ struct Tuning {
     int32_t buckets;                        // 0: no length bucketing
     int32_t generic_waves;                  // grid of the unbounded kernel
     int32_t narrow_x;                       // narrow class for drops <= narrow_x (-1: off)
+    int32_t narrow_min;                     // ... and only in batches of at least this many records
 };
 
 // Kernel launchers (xdrop_kernels.hip).  All are asynchronous on `s`.

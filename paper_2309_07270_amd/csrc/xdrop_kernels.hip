@@ -249,9 +249,10 @@ __global__ void __launch_bounds__(256) prep_kernel(BatchDev b, StoreDev st, Tuni
             mism += (uint32_t)__builtin_popcount(x);
         }
         b.seed[r] = (int)(R.k - mism) * R.match + (int)mism * R.mismatch;
-        // small drops with match 1, gap -1 and mismatch 0 / -1 / -2: two
-        // extensions per wavefront (narrow class)
-        const bool narrow = R.x <= tu.narrow_x && R.match == 1 && R.gap == -1 && R.mismatch >= -2;
+        // small drops with match 1, gap -1 and mismatch 0 / -1 / -2 in a
+        // large batch: two extensions per wavefront (narrow class)
+        const bool narrow = n >= (uint32_t)tu.narrow_min && R.x <= tu.narrow_x && R.match == 1 && R.gap == -1 &&
+                            R.mismatch >= -2;
         cls = narrow ? kNarrowClass : kAdaptiveClass;
         key0 = min(R.pos_a, pb);
         key1 = min(A.len - R.pos_a - R.k, B.len - pb - R.k);
@@ -459,6 +460,12 @@ struct Window {
         // BOUNDS: candidates only in slots lo_s .. hi_s (j <= n, i <= m)
         uint64_t imp = 0, lm[C];
         int v[C];
+        // Without clipping and with several cells per lane, the improvement
+        // test compares the lane's largest value once (a max3 tree, about C/2
+        // vector ops) instead of every cell, whose C masks would also cost
+        // C-1 scalar ORs per anti-diagonal.
+        constexpr bool LANE_MAX = !BOUNDS && C > 1;
+        int vm = NEG;
         if (COUNT) s.slots += (uint64_t)WIN;
 #pragma unroll
         for (int r = 0; r < C; ++r) {
@@ -475,12 +482,16 @@ struct Window {
             // condition costs two extra vector ops)
             const int sl = C * lane + r;
             const uint64_t inbm = BOUNDS ? ballot(sl >= lo_s) & ballot(sl <= hi_s) : ~0ull;
-            imp |= ballot(v[r] > ti) & inbm;
+            if (LANE_MAX)
+                vm = max(vm, v[r]);
+            else
+                imp |= ballot(v[r] > ti) & inbm;
             if (COUNT) s.cells += (uint64_t)__builtin_popcountll(ballot(v[r] > NEG_HALF) & inbm);
             lm[r] = ballot(v[r] >= tp) & inbm;
             const bool keep = BOUNDS ? (sl >= lo_s && sl <= hi_s && v[r] >= tp) : v[r] >= tp;
             t[r] = keep ? v[r] : NEG;
         }
+        if (LANE_MAX) imp = ballot(vm > ti);
         if (MA1 && C == 1) {
             // match weight 1: an improving cell holds exactly T_{d-1} + 1.
             // Keep the last improvement mask and pair offset of this parity,
@@ -526,12 +537,14 @@ struct Window {
             ti += G;
         } else {
             if (imp) {
-                int lm_ = NEG;
+                int lm_ = vm;
+                if (!LANE_MAX) {
 #pragma unroll
-                for (int r = 0; r < C; ++r) {
-                    const int sl = C * lane + r;
-                    const bool inb = !BOUNDS || (sl >= lo_s && sl <= hi_s);
-                    lm_ = max(lm_, inb ? v[r] : NEG);
+                    for (int r = 0; r < C; ++r) {
+                        const int sl = C * lane + r;
+                        const bool inb = !BOUNDS || (sl >= lo_s && sl <= hi_s);
+                        lm_ = max(lm_, inb ? v[r] : NEG);
+                    }
                 }
                 const int vmax = uni(wave_max(lm_));
                 // first slot (smallest lane, then smallest r) holding vmax

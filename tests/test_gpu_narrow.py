@@ -3,7 +3,8 @@ half of the lanes) against the CPU oracle, bit-exact in every result field
 and in per-record cell counts.
 
 The narrow class takes records with x <= narrow_x (20 by default) and weights
-match 1, gap -1, mismatch 0 / -1 / -2 in the persistent form.  Cases cover:
+match 1, gap -1, mismatch 0 / -1 / -2 in the persistent form, in batches of at
+least narrow_min_records records (the tests set it to 0).  Cases cover:
 tiny reads and seeds at read ends (empty extensions); bands that need the
 64-slot window and bands wider than it (the task restarts in the adaptive
 class); batches with an odd number of extensions and batches of one record
@@ -51,6 +52,13 @@ def xd():
     return xdrop
 
 
+def narrow_ctx(xd, store, **kw):
+    """A context whose narrow class takes batches of any size."""
+    ctx = xd.Context(store, **kw)
+    ctx.set_tuning(narrow_min_records=0)
+    return ctx
+
+
 def stage(xd, st, name):
     return int(st["stage_tasks"][xd.STAGE_NAMES.index(name)])
 
@@ -86,7 +94,7 @@ def test_narrow_random_bit_exact(xd, seed, lo, hi, related, n):
     ref, _ = oracle.batch(store.codes, store.off, store.length, recs)
     note(f"narrow random records seed={seed} len=[{lo},{hi}] related={related}")
     for mode in (0, 1):
-        with xd.Context(store, mode=mode) as ctx:
+        with narrow_ctx(xd, store, mode=mode) as ctx:
             res, cells, st = ctx.run(recs, count_cells=True)
         assert_same(res, cells, ref)
         if mode == 0:
@@ -104,7 +112,7 @@ def test_narrow_c1_shaped_x20(xd):
     widths = widest_bands(wl.store, wl.records[:600])
     assert np.mean((widths > 30) & (widths <= 56)) > 0.1, np.percentile(widths, [50, 90, 99])
     note("narrow class on c1-shaped records at X = 20")
-    with xd.Context(wl.store) as ctx:
+    with narrow_ctx(xd, wl.store) as ctx:
         res, cells, st = ctx.run(wl.records, count_cells=True)
     assert_same(res, cells, ref)
     assert stage(xd, st, "narrow") == 2 * len(wl.records)
@@ -117,7 +125,7 @@ def test_narrow_mixed_with_other_classes(xd):
     wl = W.make_workload("c2", pairs=4000, genome=1_000_000)
     ref, _ = oracle.batch(wl.store.codes, wl.store.off, wl.store.length, wl.records)
     note("c2-shaped mix: narrow and adaptive classes in one batch")
-    with xd.Context(wl.store) as ctx:
+    with narrow_ctx(xd, wl.store) as ctx:
         res, cells, st = ctx.run(wl.records, count_cells=True)
     assert_same(res, cells, ref)
     assert stage(xd, st, "narrow") > 0 and stage(xd, st, "adaptive") > 0
@@ -132,7 +140,7 @@ def test_narrow_odd_and_tiny_batches(xd):
     recs = W.random_records(rng, store, 13, x_choices=(3, 10, 20), weights=NARROW_WEIGHTS)
     ref, _ = oracle.batch(store.codes, store.off, store.length, recs)
     note("narrow class: batches of 1, 2, 3 and 7 records")
-    with xd.Context(store) as ctx:
+    with narrow_ctx(xd, store) as ctx:
         off = 0
         for n in (1, 2, 3, 7):
             res, cells, st = ctx.run(recs[off:off + n], count_cells=True)
@@ -144,7 +152,7 @@ def test_narrow_odd_and_tiny_batches(xd):
 def test_narrow_off_gives_the_same_results(xd):
     wl = W.make_workload("c1", pairs=2000, x_choices=(5, 15, 20), genome=1_000_000)
     note("narrow class on and off: identical results and cell counts")
-    with xd.Context(wl.store) as ctx:
+    with narrow_ctx(xd, wl.store) as ctx:
         res_on, cells_on, st_on = ctx.run(wl.records, count_cells=True)
         ctx.set_tuning(narrow_x=-1)
         assert ctx.tuning()["narrow_x"] == -1
@@ -153,3 +161,22 @@ def test_narrow_off_gives_the_same_results(xd):
         assert ctx.tuning()["narrow_x"] == 64
     assert np.array_equal(res_on, res_off) and np.array_equal(cells_on, cells_off)
     assert stage(xd, st_on, "narrow") > 0 and stage(xd, st_off, "narrow") == 0
+
+
+def test_narrow_only_in_large_batches(xd):
+    # a batch smaller than narrow_min_records runs every extension one per
+    # wavefront; from that size on the narrow class takes its records
+    wl = W.make_workload("c1", pairs=400, x_choices=(10, 20), genome=1_000_000)
+    ref, _ = oracle.batch(wl.store.codes, wl.store.off, wl.store.length, wl.records)
+    note("narrow class by batch size (narrow_min_records)")
+    with xd.Context(wl.store) as ctx:
+        assert ctx.tuning()["narrow_min_records"] == 100000
+        res0, cells0, st0 = ctx.run(wl.records, count_cells=True)
+        ctx.set_tuning(narrow_min_records=400)
+        res1, cells1, st1 = ctx.run(wl.records, count_cells=True)
+        res2, cells2, st2 = ctx.run(wl.records[:399], count_cells=True)
+    for res, cells, r in ((res0, cells0, ref), (res1, cells1, ref), (res2, cells2, ref[:399])):
+        assert_same(res, cells, r)
+    assert stage(xd, st0, "narrow") == 0 and stage(xd, st0, "adaptive") == 800
+    assert stage(xd, st1, "narrow") > 0
+    assert stage(xd, st2, "narrow") == 0 and stage(xd, st2, "adaptive") == 798

@@ -270,6 +270,7 @@ def test_bands_widen_then_narrow(xd, weights):
     note(f"bands that widen through every window class, then narrow; weights {weights}")
     with xd.Context(store) as ctx:
         assert ctx.tuning()["narrow_x"] == NARROW_X
+        ctx.set_tuning(narrow_min_records=0)   # the narrow class for a batch this small
         res, cells, st = ctx.run(recs, count_cells=True)
     assert_same(res, cells, ref)
     tasks = [int(v) for v in st["stage_tasks"][1:6]]
@@ -368,8 +369,9 @@ def test_paper_settings_k31_x15(xd):
     wl = W.make_workload("c1", pairs=3000, k=31, x_choices=(15,), genome=1_000_000)
     ref, _ = oracle.batch(wl.store.codes, wl.store.off, wl.store.length, wl.records)
     note("paper settings: k=31, X=15, 3000 c1-shaped records")
-    for mode in (0, 1):
+    for mode, narrow_min in ((0, 0), (0, 100000), (1, 0)):
         with xd.Context(wl.store, mode=mode) as ctx:
+            ctx.set_tuning(narrow_min_records=narrow_min)   # 0: two extensions per wavefront
             res, cells, _ = ctx.run(wl.records, count_cells=True)
         assert_same(res, cells, ref)
     assert np.all(res["seed_score"] == 31)
