@@ -198,6 +198,9 @@ typedef struct {
     int32_t narrow_min_records;   /* ... only in batches of at least this many records (>= 0):
                                      a smaller batch has too few such extensions to hide the
                                      narrow stage's tail                                      */
+    int32_t wide_waves;           /* wavefronts per extension for bands of 1281-2048 cells: 1
+                                     (32 cells per lane), 2 or 4 (a workgroup shares the
+                                     window; other values are rounded down to these)          */
 } xdrop_tuning;
 
 /* Current launch parameters of a context. */

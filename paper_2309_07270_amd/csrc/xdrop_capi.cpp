@@ -189,6 +189,10 @@ Tuning default_tuning()
     // stage's tail (its longest extension), which then adds to the adaptive
     // stage's own: one wavefront per extension finishes such a batch sooner
     t.narrow_min = 100000;
+    // 2048-slot class: two wavefronts share a window of 2 x 1024 slots (three
+    // such wavefronts per SIMD) instead of one wavefront of 32 cells per lane
+    // (one per SIMD)
+    t.wide_waves = 2;
     return t;
 }
 
@@ -212,6 +216,8 @@ bool load_tuning(const std::string &path, Tuning &t)
             f >> t.narrow_x;
         } else if (key == "narrow_min_records") {
             f >> t.narrow_min;
+        } else if (key == "wide_waves") {
+            f >> t.wide_waves;
         } else {
             std::string rest;
             std::getline(f, rest);
@@ -420,7 +426,7 @@ void enqueue_kernels(xdrop_ctx *c, const Tuning &tu, const GenericScratch &gs, c
     launch_adaptive(b, c->st, tu, persistent ? resident : std::max<uint32_t>(2 * n, 4), count, s);
     if (ev) HIP_TRY(hipEventRecord(ev[2 + kAdaptiveClass], s));
     for (int w = 0; w < kWideClasses; ++w) {
-        launch_wide(w, b, c->st, (uint32_t)c->cus * 8u, count, s);
+        launch_wide(w, b, c->st, (uint32_t)c->cus, tu.wide_waves, count, s);
         if (ev) HIP_TRY(hipEventRecord(ev[2 + kAdaptiveClass + 1 + w], s));
     }
     launch_generic(b, c->st, gs.base, gs.stride, gs.blocks, count, s);
@@ -718,6 +724,7 @@ void clamp_tuning(Tuning &t)
                       kGenericBlockWaves * kGenericBlockWaves;
     t.narrow_x = std::min(std::max(t.narrow_x, -1), kNarrowMaxX);
     t.narrow_min = std::max(t.narrow_min, 0);
+    t.wide_waves = t.wide_waves >= 4 ? 4 : t.wide_waves >= 2 ? 2 : 1;
 }
 
 // new launch parameters: captured graphs hold the old ones; the unbounded
@@ -854,7 +861,8 @@ bool write_tuning(const std::string &path, const Tuning &t)
       << "buckets " << t.buckets << "\n"
       << "generic_waves " << t.generic_waves << "\n"
       << "narrow_x " << t.narrow_x << "\n"
-      << "narrow_min_records " << t.narrow_min << "\n";
+      << "narrow_min_records " << t.narrow_min << "\n"
+      << "wide_waves " << t.wide_waves << "\n";
     return (bool)f;
 }
 
@@ -1075,6 +1083,7 @@ xdrop_status xdrop_get_tuning(const xdrop_ctx *c, xdrop_tuning *out)
     out->generic_waves = c->tune.generic_waves;
     out->narrow_x = c->tune.narrow_x;
     out->narrow_min_records = c->tune.narrow_min;
+    out->wide_waves = c->tune.wide_waves;
     return XDROP_OK;
 }
 
@@ -1091,6 +1100,7 @@ xdrop_status xdrop_set_tuning(xdrop_ctx *c, const xdrop_tuning *in)
     t.generic_waves = in->generic_waves;
     t.narrow_x = in->narrow_x;
     t.narrow_min = in->narrow_min_records;
+    t.wide_waves = in->wide_waves;
     clamp_tuning(t);
     try {
         apply_tuning(c, t);
@@ -1153,6 +1163,8 @@ xdrop_status xdrop_autotune(xdrop_ctx *c, const xdrop_record *recs, size_t n, co
         // two extensions per wavefront for drops up to: off, 15, 20, 30, 40
         {{{-1, 0}, {15, 0}, {20, 0}, {30, 0}, {40, 0}},
          [](Tuning &t, std::pair<int, int> v) { t.narrow_x = v.first; }},
+        // wavefronts per extension of bands of 1281-2048 cells: 1, 2 or 4
+        {{{1, 0}, {2, 0}, {4, 0}}, [](Tuning &t, std::pair<int, int> v) { t.wide_waves = v.first; }},
     };
     const Tuning start = c->tune;
     Tuning best = start;

@@ -38,7 +38,9 @@ struct TaskOut {
 //      width following the band;
 //   2  register window of 8, 12, 16 or 20 cells per lane (512..1280 slots),
 //      the width following the band;
-//   3  register window of 24 or 32 cells per lane (1536..2048 slots);
+//   3  register window of 2048 slots: one wavefront of 24 or 32 cells per
+//      lane (1536..2048 slots), or 2 or 4 wavefronts of a workgroup sharing
+//      the window (tuning knob wide_waves);
 //   4  unbounded band: one workgroup per extension, anti-diagonals in an LDS
 //      ring (global memory beyond 8192 cells).
 constexpr int kNarrowClass = 0;
@@ -123,6 +125,7 @@ struct Tuning {
     int32_t generic_waves;                  // grid of the unbounded kernel
     int32_t narrow_x;                       // narrow class for drops <= narrow_x (-1: off)
     int32_t narrow_min;                     // ... and only in batches of at least this many records
+    int32_t wide_waves;                     // wavefronts per extension in the 2048-slot class: 1, 2 or 4
 };
 
 // Kernel launchers (xdrop_kernels.hip).  All are asynchronous on `s`.
@@ -136,7 +139,7 @@ void launch_narrow(const BatchDev &b, const StoreDev &st, const Tuning &tu, uint
                    hipStream_t s);
 void launch_adaptive(const BatchDev &b, const StoreDev &st, const Tuning &tu, uint32_t grid_waves,
                      bool count_cells, hipStream_t s);
-void launch_wide(int which, const BatchDev &b, const StoreDev &st, uint32_t grid_waves, bool count_cells,
+void launch_wide(int which, const BatchDev &b, const StoreDev &st, uint32_t cus, int ext_waves, bool count_cells,
                  hipStream_t s);
 // Unbounded kernel: one workgroup of kGenericBlockWaves wavefronts per
 // extension; `blocks` workgroups, each with three anti-diagonals of

@@ -1751,6 +1751,486 @@ wide_kernel(BatchDev b, StoreDev st, int cls)
 }
 
 // ---------------------------------------------------------------------------
+// Second wide class with several wavefronts per extension (tuning knob
+// wide_waves = W of 2 or 4; 1 runs wide_kernel<1> above).  The class's
+// 2048-slot window is split into W segments of 64*C slots, one per
+// wavefront of a workgroup: global slot S = 64*C*w + C*lane + r, cell
+// i = o_d + S as in Window.  Every anti-diagonal ends with an exchange
+// through LDS and one barrier: each wavefront publishes whether one of its
+// cells beat the improvement threshold, the edge cell its neighbour reads as
+// a gap predecessor on the next anti-diagonal (the rotate brings it in from
+// the wrong wavefront), and, on even anti-diagonals, whether a window edge
+// slot went live.  With match 1 an improving cell holds exactly T + 1, so
+// the flags decide the threshold; other weights take a second exchange of
+// the wavefronts' largest values on improving anti-diagonals.  Block control
+// (band, re-centring, end cell, two dead anti-diagonals, hand-over) uses
+// group-wide reductions, so every wavefront takes every branch and every
+// barrier together.  The window has one width: a band that outgrows it goes
+// to the unbounded kernel with its state.
+// ---------------------------------------------------------------------------
+constexpr int kGroupWin = 64 * kWideC[1];   // slots of the window (the class limit)
+
+template <int W>
+struct GroupShared {
+    int win[2 * kGroupWin];   // anti-diagonals d-1, d-2 of the window (re-centring, resume, hand-over)
+    int xch[2][W][2];         // per parity of d and wavefront: flags, edge cell
+    int vmx[W];               // largest values on an improving anti-diagonal (weights other than match 1)
+    int red[W][4];            // block-level reductions
+    uint32_t task[2];         // task taken by wavefront 0: queue index
+};
+
+template <int C, int W, bool COUNT, bool MA1, bool SIGF>
+struct GroupWindow {
+    static constexpr int SEG = 64 * C;   // slots per wavefront
+    static constexpr int WIN = W * SEG;
+    static constexpr int STRIDE = WIN;
+    static constexpr int NWC = (C + UMAX + 16) / 16;   // words of codes per lane and block
+    static_assert(WIN == kGroupWin, "one window width: the class limit");
+
+    int Z1[C], Z2[C];
+    uint32_t mmo[C], mme[C];
+    int wv;                  // this wavefront's segment (wave-uniform)
+    int s0;                  // its first slot, SEG * wv
+    int nb;                  // neighbour's edge cell for the next anti-diagonal (same in every lane)
+    // end cell: last anti-diagonal with an improving cell in this segment
+    // since the last resolve(); MA1: its improvement mask over lanes and,
+    // per lane, the first improving r; other weights: the cell's slot
+    int last_d, last_r, last_s;
+    uint64_t last_imp;
+    GroupShared<W> *sh;
+
+    // group-wide reduction of up to four values per wavefront: every
+    // wavefront sees all of them (q = 0 .. W-1) after the call
+    __device__ __forceinline__ void publish(int a, int b2 = 0, int c = 0, int e = 0)
+    {
+        if (lane_id() == 0) {
+            sh->red[wv][0] = a; sh->red[wv][1] = b2; sh->red[wv][2] = c; sh->red[wv][3] = e;
+        }
+        __syncthreads();
+    }
+    __device__ __forceinline__ int got(int q, int k) const { return uni(sh->red[q][k]); }
+    __device__ __forceinline__ void done_reading() const { __syncthreads(); }
+
+    __device__ __forceinline__ void init(XState &s)
+    {
+        const int lane = lane_id();
+        const int c0 = WIN / 2 - 1;
+        s.base = -c0;
+        s.d = 1;
+        s.T = 0; s.bi = 0; s.bj = 0; s.cells = 0; s.slots = 0;
+        s.mn = s.mx = c0;
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            Z1[r] = (s0 + C * lane + r == c0) ? 0 : NEG;
+            Z2[r] = NEG;
+        }
+    }
+
+    // segment -> the shared window buffer, by global slot
+    __device__ __forceinline__ void save()
+    {
+        const int lane = lane_id();
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            sh->win[s0 + C * lane + r] = Z1[r];
+            sh->win[STRIDE + s0 + C * lane + r] = Z2[r];
+        }
+        __syncthreads();
+    }
+
+    // take over a window of from_win slots in the shared buffer: new slot S
+    // holds old slot S + delta
+    __device__ __forceinline__ void load(int from_win, int delta)
+    {
+        const int lane = lane_id();
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            const int q = s0 + C * lane + r + delta;
+            const bool ok = q >= 0 && q < from_win;
+            const int qc = ok ? q : 0;
+            const int a = sh->win[qc], b2 = sh->win[STRIDE + qc];
+            Z1[r] = ok ? a : NEG;
+            Z2[r] = ok ? b2 : NEG;
+        }
+        __syncthreads();   // read by every wavefront before the buffer is written again
+    }
+
+    // live slots over the last two anti-diagonals, group-wide; false when both are dead
+    __device__ bool band(int &mn, int &mx)
+    {
+        int lmn = 1 << 30, lmx = -1;
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            const uint64_t u = ballot(max(Z1[r], Z2[r]) > NEG_HALF);
+            if (u) {
+                lmn = min(lmn, s0 + C * __builtin_ctzll(u) + r);
+                lmx = max(lmx, s0 + C * (63 - __builtin_clzll(u)) + r);
+            }
+        }
+        publish(lmn, lmx);
+        mn = 1 << 30;
+        mx = -1;
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            mn = min(mn, got(q, 0));
+            mx = max(mx, got(q, 1));
+        }
+        done_reading();
+        return mx >= 0;
+    }
+
+    // before the first (odd) anti-diagonal of a block: lane 0 of each
+    // segment needs the last slot of the previous segment's d-1
+    __device__ __forceinline__ void prime()
+    {
+        publish(__builtin_amdgcn_readlane(Z1[C - 1], 63));
+        nb = wv > 0 ? got(wv - 1, 0) : NEG;
+        done_reading();
+    }
+
+    // One anti-diagonal d.  Returns whether a window edge slot (0, 1, WIN-2,
+    // WIN-1) holds a live cell of d (even d; false for odd d).
+    template <bool ODD, bool BOUNDS>
+    __device__ __forceinline__ bool step(XState &s, int d, uint32_t ub, int &tp, int &ti, int sm, int nd, int G,
+                                         int X, int lo_s = 0, int hi_s = 0)
+    {
+        const int lane = lane_id();
+        int t[C];
+        if (ODD) {
+            // slots S-1 and S: lane 0 takes the previous segment's last slot
+            int x = __builtin_amdgcn_mov_dpp(Z1[C - 1], 0x13C, 0xf, 0xf, true);   // wave_ror:1
+            x = lane == 0 ? nb : x;
+            t[0] = max(x, Z1[0]);
+#pragma unroll
+            for (int r = 1; r < C; ++r) t[r] = max(Z1[r - 1], Z1[r]);
+        } else {
+            // slots S and S+1: lane 63 takes the next segment's first slot
+#pragma unroll
+            for (int r = 0; r < C - 1; ++r) t[r] = max(Z1[r], Z1[r + 1]);
+            int x = __builtin_amdgcn_mov_dpp(Z1[0], 0x134, 0xf, 0xf, true);       // wave_rol:1
+            x = lane == 63 ? nb : x;
+            t[C - 1] = max(x, Z1[C - 1]);
+        }
+        int v[C];
+        int vm = NEG;
+        uint64_t le = 0, re = 0;   // live masks of the window's edge slots (even d)
+        if (COUNT) s.slots += (uint64_t)SEG;
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            const uint32_t w = ODD ? mmo[r] : mme[r];
+            int sig;
+            if (SIGF) {
+                sig = (int)__builtin_amdgcn_ubfe(w, ub, 2u);
+            } else {
+                const int bit = (int)__builtin_amdgcn_ubfe(w, ub, 1u);
+                sig = __mul24(bit, nd) + sm;          // sigma - 2*gap
+            }
+            v[r] = max(t[r], Z2[r] + sig);
+            const int sl = s0 + C * lane + r;
+            const bool inb = !BOUNDS || (sl >= lo_s && sl <= hi_s);
+            vm = max(vm, inb ? v[r] : NEG);
+            if (COUNT) s.cells += (uint64_t)__builtin_popcountll(ballot(inb && v[r] > NEG_HALF));
+            const bool keep = inb && v[r] >= tp;
+            if (!ODD && (r == 0 || r == 1)) le |= ballot(keep);
+            if (!ODD && (r == C - 2 || r == C - 1)) re |= ballot(keep);
+            t[r] = keep ? v[r] : NEG;
+        }
+        const uint64_t imp = ballot(vm > ti);
+        int fl = imp ? 1 : 0;
+        if (!ODD && ((wv == 0 && (le & 1ull)) || (wv == W - 1 && (re >> 63)))) fl |= 2;
+        // the edge cell the neighbour needs next: after an odd d the first
+        // slot (for the previous segment), after an even d the last slot
+        const int edge = ODD ? __builtin_amdgcn_readlane(t[0], 0) : __builtin_amdgcn_readlane(t[C - 1], 63);
+        int *x = sh->xch[ODD ? 1 : 0][wv];
+        if (lane == 0) {
+            x[0] = fl;
+            x[1] = edge;
+        }
+        __syncthreads();
+        int f = 0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) f |= sh->xch[ODD ? 1 : 0][q][0];
+        f = uni(f);
+        if (ODD) nb = wv < W - 1 ? uni(sh->xch[1][wv + 1][1]) : NEG;
+        else nb = wv > 0 ? uni(sh->xch[0][wv - 1][1]) : NEG;
+        if (MA1) {
+            if (imp) {
+                // first improving slot of this segment: smallest lane, then smallest r
+                last_d = d;
+                last_imp = imp;
+                int rl = C - 1;
+#pragma unroll
+                for (int r = C - 1; r >= 0; --r) {
+                    const int sl = s0 + C * lane + r;
+                    const bool inb = !BOUNDS || (sl >= lo_s && sl <= hi_s);
+                    if (inb && v[r] > ti) rl = r;
+                }
+                last_r = rl;
+            }
+            const int inc = f & 1;
+            tp += G + inc;
+            ti += G + inc;
+        } else {
+            if (f & 1) {
+                // the group's largest value of d is the new threshold
+                const int wmax = uni(wave_max(vm));
+                if (lane == 0) sh->vmx[wv] = wmax;
+                __syncthreads();
+                int gmax = NEG;
+#pragma unroll
+                for (int q = 0; q < W; ++q) gmax = max(gmax, uni(sh->vmx[q]));
+                if (wmax == gmax) {
+                    // first slot of this segment holding it
+                    int rl = C;
+#pragma unroll
+                    for (int r = C - 1; r >= 0; --r) {
+                        const int sl = s0 + C * lane + r;
+                        const bool inb = !BOUNDS || (sl >= lo_s && sl <= hi_s);
+                        if (inb && v[r] == gmax) rl = r;
+                    }
+                    const uint64_t any = ballot(rl < C);
+                    const int l = __builtin_ctzll(any);
+                    last_d = d;
+                    last_s = s0 + C * l + __builtin_amdgcn_readlane(rl, l);
+                }
+                tp += gmax - ti;
+                ti = gmax;
+            }
+            tp += G;
+            ti += G;
+        }
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            Z2[r] = Z1[r];
+            Z1[r] = t[r];
+        }
+        return (f & 2) != 0;
+    }
+
+    // end cell of the last improvement since the previous call: the last
+    // anti-diagonal any segment improved on, then its smallest slot
+    __device__ void resolve(XState &s)
+    {
+        int ld = -1, ls = 0;
+        if (last_d >= 0) {
+            ld = last_d;
+            if (MA1) {
+                const int l = __builtin_ctzll(last_imp);
+                ls = s0 + C * l + __builtin_amdgcn_readlane(last_r, l);
+            } else {
+                ls = last_s;
+            }
+        }
+        publish(ld, ls);
+        int gd = -1, gs = 0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            const int qd = got(q, 0), qs = got(q, 1);
+            if (qd > gd) { gd = qd; gs = qs; }   // segments in slot order: the first wins a tie
+        }
+        done_reading();
+        if (gd >= 0) {
+            s.bi = s.base + (gd >> 1) + gs;
+            s.bj = gd - s.bi;
+        }
+        last_d = -1;
+    }
+
+    template <bool BOUNDS>
+    __device__ __forceinline__ uint32_t pairs(XState &s, int d0, int np, int &tp, int &ti, int sm, int nd, int G,
+                                              int X, int m, int n)
+    {
+        // clipping bounds in global slots, as in Window::pairs
+        const int o0 = s.base + (d0 >> 1);
+        int lo_s = d0 - n - o0, hi_s = m - o0;
+        const uint32_t ube = 2u * (uint32_t)np;
+        uint32_t ub = 0;
+        do {
+            step<true, BOUNDS>(s, d0 + (int)ub, ub, tp, ti, sm, nd, G, X, lo_s, hi_s);
+            const bool e = step<false, BOUNDS>(s, d0 + (int)ub + 1, ub, tp, ti, sm, nd, G, X, lo_s, hi_s - 1);
+            ++lo_s;
+            --hi_s;
+            ub += e ? 66u : 2u;   // a live edge slot ends the block (2 * UMAX < 64)
+        } while (ub < ube);
+        return ub;
+    }
+
+    // Advance the extension block by block (Window::run with group-wide
+    // control).  Returns kDone, or kGrow with the window saved to the shared
+    // buffer and s.mn / s.mx set.
+    __device__ uint32_t run(const uint32_t *__restrict__ Wd, const Geo &g, int X, int ma, int mi, int gap,
+                            XState &s)
+    {
+        const int lane = lane_id();
+        const int m = g.m, n = g.n;
+        const int G = -gap;
+        const int sm = ma + 2 * G;
+        const int sx = mi + 2 * G;
+        const int nd = mi - ma;
+        const int dend = m + n;
+        const uint32_t *aseq = Wd + (g.abase >> 4), *bseq = Wd + (g.bbase >> 4);
+        const int aph = (int)(g.abase & 15), bph = (int)(g.bbase & 15);
+        last_d = -1;
+        int ti = s.T + G * s.d;
+        while (s.d <= dend) {
+            int mn, mx;
+            if (!band(mn, mx)) break;                 // two dead anti-diagonals
+            const int width = mx - mn + 1;
+            if (width + 4 > WIN) {
+                save();
+                s.mn = mn;
+                s.mx = mx;
+                s.T = ti - G * s.d;
+                return kGrow;
+            }
+            if (min(mn, WIN - 1 - mx) < kRecentre) {
+                const int delta = mn - (WIN - width) / 2;
+                save();
+                load(WIN, delta);
+                s.base += delta;
+            }
+            const int d = s.d;
+            const int P = min(UMAX, (dend - d + 2) >> 1);
+            const int e0 = (d - 1) >> 1;
+            const int A0 = s.base + e0 - 1;
+            const int B0 = e0 - s.base;
+            uint32_t aw[NWC], bw[NWC];
+            load_codes<NWC>(aseq, aph, A0 + s0 + C * lane, aw);
+            load_codes<NWC>(bseq, bph, B0 - s0 - C * lane - (C - 1), bw);
+#pragma unroll
+            for (int r = 0; r < C; ++r) {
+                const uint32_t bb = codes16<NWC>(bw, C - 1 - r);
+                const uint32_t xo = codes16<NWC>(aw, r) ^ bb;
+                const uint32_t xe = codes16<NWC>(aw, r + 1) ^ bb;
+                const uint32_t mo = (xo | (xo >> 1)) & 0x55555555u;
+                const uint32_t me = (xe | (xe >> 1)) & 0x55555555u;
+                uint32_t fo = mo, fe = me;
+                if (SIGF) {
+                    const uint32_t base_f = (uint32_t)sm * 0x55555555u;
+                    const uint32_t k = (uint32_t)(sm ^ sx);
+                    fo = base_f ^ ((k & 1u) ? mo : 0u) ^ ((k & 2u) ? (mo << 1) : 0u);
+                    fe = base_f ^ ((k & 1u) ? me : 0u) ^ ((k & 2u) ? (me << 1) : 0u);
+                }
+                mmo[r] = fo;
+                mme[r] = fe;
+            }
+            int tp = ti - X;
+            const int dlast = d + 2 * P - 1;
+            const int o_last = s.base + (dlast >> 1);
+            const bool fast = o_last + WIN - 2 <= m && o_last >= dlast - n;
+            prime();
+            const uint32_t ub = fast ? pairs<false>(s, d, P, tp, ti, sm, nd, G, X, m, n)
+                                     : pairs<true>(s, d, P, tp, ti, sm, nd, G, X, m, n);
+            resolve(s);
+            s.d = d + 2 * ((int)(ub & 63u) >> 1);
+        }
+        s.T = ti - G * s.d;
+        return kDone;
+    }
+};
+
+// One extension in the group window: fresh, or resumed from the state the
+// first wide class carried over.  Cell and slot-step counts are summed over
+// the wavefronts into wavefront 0's state.
+template <int C, int W, bool COUNT, bool MA1, bool SIGF>
+__device__ uint32_t group_run(const BatchDev &b, const StoreDev &st, const Task &k, GroupShared<W> &sh, int wv,
+                              XState &s, uint32_t coff)
+{
+    GroupWindow<C, W, COUNT, MA1, SIGF> w;
+    w.sh = &sh;
+    w.wv = wv;
+    w.s0 = w.SEG * wv;
+    if (coff != kNoCarry) {
+        const int32_t *rec = b.carry + coff;
+        carry_state(rec, s);
+        const int from_win = carry_word(rec, CarryLayout::kWin);   // <= 1280 slots
+        for (int q = (int)threadIdx.x; q < from_win; q += 64 * W) {
+            sh.win[q] = rec[CarryLayout::kHeader + q];
+            sh.win[w.STRIDE + q] = rec[CarryLayout::kHeader + from_win + q];
+        }
+        __syncthreads();
+        const int width = s.mx - s.mn + 1;
+        const int delta = s.mn - (w.WIN - width) / 2;
+        s.base += delta;
+        w.load(from_win, delta);
+    } else {
+        w.init(s);
+    }
+    if (COUNT && wv != 0) { s.cells = 0; s.slots = 0; }   // wavefront 0 holds the carried totals
+    const uint32_t stt = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, s);
+    if (COUNT) {
+        w.publish((int)(uint32_t)s.cells, (int)(uint32_t)(s.cells >> 32), (int)(uint32_t)s.slots,
+                  (int)(uint32_t)(s.slots >> 32));
+        uint64_t c = 0, sl = 0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            c += (uint64_t)(uint32_t)w.got(q, 0) | ((uint64_t)(uint32_t)w.got(q, 1) << 32);
+            sl += (uint64_t)(uint32_t)w.got(q, 2) | ((uint64_t)(uint32_t)w.got(q, 3) << 32);
+        }
+        w.done_reading();
+        s.cells = c;
+        s.slots = sl;
+    }
+    return stt;
+}
+
+// The second wide class with W wavefronts per extension, one workgroup per
+// extension; wavefront 0 takes the tasks and writes results and hand-overs.
+template <int C, int W, bool COUNT>
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 2 ? 3 : 4)))
+group_kernel(BatchDev b, StoreDev st, int cls)
+{
+    __shared__ GroupShared<W> sh;
+    const int wv = uni((int)(threadIdx.x >> 6));
+    const uint32_t qcap = 2u * b.cap;
+    const uint32_t cnt = b.ctr[CtrLayout::kCount + cls];
+    for (;;) {
+        if (wv == 0) {
+            const uint32_t idx = wave_fetch_add(&b.ctr[CtrLayout::kHead + cls], 1u);
+            if (lane_id() == 0) sh.task[0] = idx;
+        }
+        __syncthreads();
+        const uint32_t idx = (uint32_t)uni((int)sh.task[0]);
+        __syncthreads();         // read by every wavefront before wavefront 0 writes it again
+        if (idx >= cnt) break;   // uniform over the workgroup
+        const uint32_t t = (uint32_t)uni((int)b.qbuf[cls * qcap + idx]);
+        const uint32_t coff = (uint32_t)uni((int)b.qstate[cls * qcap + idx]);
+        const Task k = load_task(b.recs, st.reads, t);
+        XState s;
+        uint32_t status;
+        if (k.ma != 1)
+            status = group_run<C, W, COUNT, false, false>(b, st, k, sh, wv, s, coff);
+        else if (sigma_fits_2bits(k))
+            status = group_run<C, W, COUNT, true, true>(b, st, k, sh, wv, s, coff);
+        else
+            status = group_run<C, W, COUNT, true, false>(b, st, k, sh, wv, s, coff);
+        if (wv == 0) {
+            if (status == kDone) {
+                TaskOut o;
+                o.score = s.T; o.i = s.bi; o.j = s.bj; o.status = (uint32_t)cls; o.cells = s.cells; o.slots = s.slots;
+                b.tout[t] = o;
+            } else {
+                // the window (saved by run) goes to the unbounded kernel
+                const uint32_t off = carry_alloc(b, CarryLayout::kHeader + 2 * kGroupWin);
+                if (off != kNoCarry) carry_store(b, off, s, sh.win, kGroupWin, kGroupWin);
+                const uint32_t pos = wave_fetch_add(&b.ctr[CtrLayout::kCount + cls + 1], 1u);
+                b.qbuf[(cls + 1) * qcap + pos] = t;
+                b.qstate[(cls + 1) * qcap + pos] = off;
+                if (COUNT && off != kNoCarry && lane_id() == 0) {
+                    // as in wide_kernel: each stage's sums hold only its own work
+                    const int stg = 1 + cls;
+                    atomicAdd(&b.stage_sum[stg], (unsigned long long)s.cells);
+                    atomicAdd(&b.stage_sum[stg + 1], 0ull - (unsigned long long)s.cells);
+                    atomicAdd(&b.stage_sum[16 + stg], (unsigned long long)s.slots);
+                    atomicAdd(&b.stage_sum[16 + stg + 1], 0ull - (unsigned long long)s.slots);
+                }
+            }
+        }
+        __syncthreads();   // the shared window is read by wavefront 0 before the next task writes it
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Unbounded X-drop extension.  One workgroup of 1024 threads runs one
 // extension: its threads sweep the candidate range of an anti-diagonal
 // together, and one block reduction per anti-diagonal gives the live range,
@@ -2161,12 +2641,26 @@ static void launch_wide_c(const BatchDev &b, const StoreDev &st, int cls, uint32
         hipLaunchKernelGGL((wide_kernel<L, false>), dim3(blocks), dim3(256), lds, s, b, st, cls);
 }
 
-void launch_wide(int which, const BatchDev &b, const StoreDev &st, uint32_t grid_waves, bool count_cells,
+template <int C, int W>
+static void launch_group_c(const BatchDev &b, const StoreDev &st, int cls, uint32_t grid_waves, bool count,
+                           hipStream_t s)
+{
+    const uint32_t blocks = (grid_waves + W - 1) / W;
+    if (count)
+        hipLaunchKernelGGL((group_kernel<C, W, true>), dim3(blocks), dim3(64 * W), 0, s, b, st, cls);
+    else
+        hipLaunchKernelGGL((group_kernel<C, W, false>), dim3(blocks), dim3(64 * W), 0, s, b, st, cls);
+}
+
+void launch_wide(int which, const BatchDev &b, const StoreDev &st, uint32_t cus, int ext_waves, bool count_cells,
                  hipStream_t s)
 {
     static_assert(kWideClasses == 2, "wide classes");
-    if (which == 0) launch_wide_c<0>(b, st, kAdaptiveClass + 1 + which, grid_waves, count_cells, s);
-    else launch_wide_c<1>(b, st, kAdaptiveClass + 1 + which, grid_waves, count_cells, s);
+    const int cls = kAdaptiveClass + 1 + which;
+    if (which == 0) launch_wide_c<0>(b, st, cls, cus * 8u, count_cells, s);
+    else if (ext_waves == 2) launch_group_c<16, 2>(b, st, cls, cus * 12u, count_cells, s);
+    else if (ext_waves == 4) launch_group_c<8, 4>(b, st, cls, cus * 16u, count_cells, s);
+    else launch_wide_c<1>(b, st, cls, cus * 8u, count_cells, s);
 }
 
 void launch_generic(const BatchDev &b, const StoreDev &st, int32_t *scratch, uint64_t stride, uint32_t blocks,

@@ -80,7 +80,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("grow_margin", ctypes.c_int32), ("shrink_margin", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("buckets", ctypes.c_int32),
                 ("generic_waves", ctypes.c_int32), ("narrow_x", ctypes.c_int32),
-                ("narrow_min_records", ctypes.c_int32)]
+                ("narrow_min_records", ctypes.c_int32), ("wide_waves", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -172,12 +172,14 @@ def test_unbounded_resume_into_used_ring(xd):
     assert_same(res, cells, ref)
 
 
-def test_class_hand_over_pool_overflow(xd):
+@pytest.mark.parametrize("wide_waves", [1, 2, 4])
+def test_class_hand_over_pool_overflow(xd, wide_waves):
     # Every right extension here outgrows the 1024- and 2048-slot windows
     # (X = 2^30, ~2.3 kb on both sides), so each record hands about 6,200
     # words of window state to wider classes: far more than a 1,024-record
     # batch's carry pool holds.  Early tasks resume from their carried
-    # state, later ones restart; both must give the oracle's results.
+    # state, later ones restart; both must give the oracle's results, with
+    # one, two or four wavefronts per extension in the 2048-slot class.
     rng = np.random.Generator(np.random.PCG64(44))
     base = rng.integers(0, 4, 2700).astype(np.uint8)
     reads, lens = [], []
@@ -200,11 +202,54 @@ def test_class_hand_over_pool_overflow(xd):
     recs["x"] = np.where(rng.random(n) < 0.8, 1 << 30, 400)
     recs["match"], recs["mismatch"], recs["gap"] = 1, -1, -1
     ref, _ = oracle.batch(store.codes, store.off, store.length, recs)
-    note("class hand-over beyond the carry pool: 200 records, X = 2^30 / 400, ~2.3 kb extensions")
+    note(f"class hand-over beyond the carry pool: 200 records, X = 2^30 / 400, ~2.3 kb extensions, "
+         f"wide_waves {wide_waves}")
     with xd.Context(store) as ctx:
+        ctx.set_tuning(wide_waves=wide_waves)
         res, cells, stats = ctx.run(recs, count_cells=True)
     assert_same(res, cells, ref)
     assert int(stats["stage_tasks"][xd.STAGE_NAMES.index("generic")]) > 0   # the unbounded class ran
+
+
+@pytest.mark.parametrize("weights", [(1, -1, -1), (1, -2, -1), (2, -3, -2)])
+def test_group_window_random(xd, weights):
+    # related 2-4 kb reads (20 % substitutions) at drops that take many bands
+    # through the 1281-2048-cell class: the window shared by 2 and 4
+    # wavefronts gives the oracle's results, as one wavefront does; seeds
+    # anywhere, both strands, short reads among them
+    rng = np.random.Generator(np.random.PCG64(300 + weights[1]))
+    base = rng.integers(0, 4, 4200).astype(np.uint8)
+    reads = []
+    for q in range(16):
+        r = base[rng.integers(0, 200):].copy()
+        r = r[:rng.integers(300 if q < 2 else 2000, r.size + 1)]
+        flip = rng.random(r.size) < 0.2
+        r[flip] = (r[flip] + rng.integers(1, 4, int(flip.sum()))) % 4
+        reads.append(r)
+    lens = np.array([r.size for r in reads])
+    store = W.ReadStore(np.concatenate(reads), np.concatenate([[0], np.cumsum(lens)[:-1]]), lens)
+    n = 160
+    recs = np.zeros(n, W.RECORD_DTYPE)
+    recs["read_a"] = rng.integers(0, 16, n)
+    recs["read_b"] = (recs["read_a"] + rng.integers(1, 16, n)) % 16
+    recs["k"] = rng.integers(1, 20, n)
+    for i in range(n):
+        la, lb = lens[recs["read_a"][i]], lens[recs["read_b"][i]]
+        recs["pos_a"][i] = rng.integers(0, la - recs["k"][i] + 1)
+        recs["pos_b"][i] = rng.integers(0, lb - recs["k"][i] + 1)
+    recs["strand"] = rng.integers(0, 2, n)
+    recs["x"] = rng.choice([300, 800, 1500, 3000, 1 << 30], n)
+    recs["match"], recs["mismatch"], recs["gap"] = weights
+    ref, _ = oracle.batch(store.codes, store.off, store.length, recs)
+    note(f"group window, random related reads, weights {weights}")
+    with xd.Context(store) as ctx:
+        for ww in (2, 4, 1):
+            ctx.set_tuning(wide_waves=ww)
+            res, cells, st = ctx.run(recs, count_cells=True)
+            assert_same(res, cells, ref)
+            assert int(st["stage_tasks"][xd.STAGE_NAMES.index("wide2048")]) > 0
+            sc = np.array(st["stage_cells"], np.uint64)
+            assert int(sc.sum()) == int(cells.sum())
 
 
 # Window classes by the widest live range of an extension (from the oracle):
@@ -229,14 +274,16 @@ WIDEN_NARROW_CASES = {
 }
 
 
+@pytest.mark.parametrize("wide_waves", [1, 2, 4])
 @pytest.mark.parametrize("weights", sorted(WIDEN_NARROW_CASES))
-def test_bands_widen_then_narrow(xd, weights):
+def test_bands_widen_then_narrow(xd, weights, wide_waves):
     # A random 2.5-3.2 kb prefix, then 6 kb shared by every read.  Through
     # the random part the band widens: the windows step up their ladders and
     # hand over to wider classes.  In the shared part the band collapses to
     # about X, so the windows step back down.  The three weight sets take the
     # three step variants (sigma in 2-bit fields; match 1 with a wider sigma;
-    # general weights).  Seeds sit at position 0, so every left extension is
+    # general weights), and the 2048-slot class runs with one, two or four
+    # wavefronts per extension.  Seeds sit at position 0, so every left extension is
     # empty and every right extension runs the whole reads.  For each weight
     # set the cases reach every class, and each class must complete exactly
     # the extensions whose widest band (from the oracle) it holds.
@@ -270,7 +317,8 @@ def test_bands_widen_then_narrow(xd, weights):
     note(f"bands that widen through every window class, then narrow; weights {weights}")
     with xd.Context(store) as ctx:
         assert ctx.tuning()["narrow_x"] == NARROW_X
-        ctx.set_tuning(narrow_min_records=0)   # the narrow class for a batch this small
+        ctx.set_tuning(narrow_min_records=0, wide_waves=wide_waves)   # narrow class for a batch this small
+        assert ctx.tuning()["wide_waves"] == wide_waves
         res, cells, st = ctx.run(recs, count_cells=True)
     assert_same(res, cells, ref)
     tasks = [int(v) for v in st["stage_tasks"][1:6]]
