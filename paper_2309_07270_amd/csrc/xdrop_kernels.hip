@@ -1770,9 +1770,9 @@ wide_kernel(BatchDev b, StoreDev st, int cls)
 // ---------------------------------------------------------------------------
 constexpr int kGroupWin = 64 * kWideC[1];   // slots of the window (the class limit)
 
-template <int W>
+template <int W, int WSLOTS>
 struct GroupShared {
-    int win[2 * kGroupWin];   // anti-diagonals d-1, d-2 of the window (re-centring, resume, hand-over)
+    int win[2 * WSLOTS];      // anti-diagonals d-1, d-2 of the window (re-centring, resume, hand-over)
     int xch[2][W][2];         // per parity of d and wavefront: flags, edge cell
     int vmx[W];               // largest values on an improving anti-diagonal (weights other than match 1)
     int red[W][4];            // block-level reductions
@@ -1785,7 +1785,8 @@ struct GroupWindow {
     static constexpr int WIN = W * SEG;
     static constexpr int STRIDE = WIN;
     static constexpr int NWC = (C + UMAX + 16) / 16;   // words of codes per lane and block
-    static_assert(WIN == kGroupWin, "one window width: the class limit");
+    static_assert(WIN <= 4096, "a lane's code window stays within the store's guard");
+    using Shared = GroupShared<W, WIN>;
 
     int Z1[C], Z2[C];
     uint32_t mmo[C], mme[C];
@@ -1797,7 +1798,7 @@ struct GroupWindow {
     // per lane, the first improving r; other weights: the cell's slot
     int last_d, last_r, last_s;
     uint64_t last_imp;
-    GroupShared<W> *sh;
+    Shared *sh;
 
     // group-wide reduction of up to four values per wavefront: every
     // wavefront sees all of them (q = 0 .. W-1) after the call
@@ -1947,10 +1948,9 @@ struct GroupWindow {
             x[1] = edge;
         }
         __syncthreads();
-        int f = 0;
-#pragma unroll
-        for (int q = 0; q < W; ++q) f |= sh->xch[ODD ? 1 : 0][q][0];
-        f = uni(f);
+        // lane q reads wavefront q's flags
+        const int fq = sh->xch[ODD ? 1 : 0][lane < W ? lane : 0][0];
+        const int f = (ballot(lane < W && (fq & 1)) ? 1 : 0) | (ballot(lane < W && (fq & 2)) ? 2 : 0);
         if (ODD) nb = wv < W - 1 ? uni(sh->xch[1][wv + 1][1]) : NEG;
         else nb = wv > 0 ? uni(sh->xch[0][wv - 1][1]) : NEG;
         if (MA1) {
@@ -2133,8 +2133,9 @@ struct GroupWindow {
 // first wide class carried over.  Cell and slot-step counts are summed over
 // the wavefronts into wavefront 0's state.
 template <int C, int W, bool COUNT, bool MA1, bool SIGF>
-__device__ uint32_t group_run(const BatchDev &b, const StoreDev &st, const Task &k, GroupShared<W> &sh, int wv,
-                              XState &s, uint32_t coff)
+__device__ uint32_t group_run(const BatchDev &b, const StoreDev &st, const Task &k,
+                              typename GroupWindow<C, W, COUNT, MA1, SIGF>::Shared &sh, int wv, XState &s,
+                              uint32_t coff)
 {
     GroupWindow<C, W, COUNT, MA1, SIGF> w;
     w.sh = &sh;
@@ -2143,7 +2144,7 @@ __device__ uint32_t group_run(const BatchDev &b, const StoreDev &st, const Task 
     if (coff != kNoCarry) {
         const int32_t *rec = b.carry + coff;
         carry_state(rec, s);
-        const int from_win = carry_word(rec, CarryLayout::kWin);   // <= 1280 slots
+        const int from_win = carry_word(rec, CarryLayout::kWin);   // a narrower class's window
         for (int q = (int)threadIdx.x; q < from_win; q += 64 * W) {
             sh.win[q] = rec[CarryLayout::kHeader + q];
             sh.win[w.STRIDE + q] = rec[CarryLayout::kHeader + from_win + q];
@@ -2180,7 +2181,8 @@ template <int C, int W, bool COUNT>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 2 ? 3 : 4)))
 group_kernel(BatchDev b, StoreDev st, int cls)
 {
-    __shared__ GroupShared<W> sh;
+    __shared__ GroupShared<W, kGroupWin> sh;
+    static_assert(64 * C * W == kGroupWin, "one window width: the class limit");
     const int wv = uni((int)(threadIdx.x >> 6));
     const uint32_t qcap = 2u * b.cap;
     const uint32_t cnt = b.ctr[CtrLayout::kCount + cls];
@@ -2425,29 +2427,17 @@ __device__ bool generic_diags(const uint32_t *__restrict__ W, const Geo &g, int 
     return true;
 }
 
-// Start of an unbounded extension: fresh (only S(0,0) = 0 live), or resumed
-// from a wide window's carried state, its live cells moved into the ring
-// (window units Z = S + |gap| * anti-diagonal back to scores).
-__device__ void generic_start(const BatchDev &b, uint32_t coff, int gap, int *P1, int *P2, GState &s)
+// Ring state of an unbounded extension resumed from a window of `win` slots
+// in window units (anti-diagonal d-1 at z1[0, win), d-2 at z2[0, win), slot
+// q of anti-diagonal e holding cell i = base + floor(e / 2) + q, Z = S +
+// |gap| * e); s.d, T, the best cell and the counts are set.  The live cells
+// go into the rings by i, as scores.
+__device__ void generic_resume(const int *z1src, const int *z2src, int win, int base, int gap, int *P1, int *P2,
+                               GState &s)
 {
     __shared__ int s_rng[4];
     const int tid = threadIdx.x;
     s.prev_dead = false;
-    if (coff == kNoCarry) {
-        s.d = 1; s.lo1 = 0; s.hi1 = 0; s.lo2 = 1; s.hi2 = 0;
-        s.T = 0; s.bi = 0; s.bj = 0; s.cells = 0; s.slots = 0;
-        if (tid == 0) P1[0] = 0;   // anti-diagonal 0: S(0,0) = 0
-        __syncthreads();
-        return;
-    }
-    const int32_t *rec = b.carry + coff;
-    s.d = rec[CarryLayout::kD];
-    s.T = rec[CarryLayout::kT];
-    s.bi = rec[CarryLayout::kBi];
-    s.bj = rec[CarryLayout::kBj];
-    s.cells = (uint64_t)(uint32_t)rec[CarryLayout::kCells] | ((uint64_t)(uint32_t)rec[CarryLayout::kCells + 1] << 32);
-    s.slots = (uint64_t)(uint32_t)rec[CarryLayout::kSlots] | ((uint64_t)(uint32_t)rec[CarryLayout::kSlots + 1] << 32);
-    const int base = rec[CarryLayout::kBase], win = rec[CarryLayout::kWin];
     if (tid == 0) { s_rng[0] = 0x7fffffff; s_rng[1] = -1; s_rng[2] = 0x7fffffff; s_rng[3] = -1; }
     // Every slot of the two rings starts dead: the anti-diagonals read any
     // slot between the live ends, and a carried band has dead cells inside
@@ -2460,7 +2450,7 @@ __device__ void generic_start(const BatchDev &b, uint32_t coff, int gap, int *P1
     const int G = -gap, d1 = s.d - 1, d2 = s.d - 2;
     const int o1 = base + (d1 >> 1), o2 = base + (d2 >> 1);   // i of slot 0 (d2 >= 0: a window ran)
     for (int q = tid; q < win; q += kGenericThreads) {
-        const int z1 = rec[CarryLayout::kHeader + q], z2 = rec[CarryLayout::kHeader + win + q];
+        const int z1 = z1src[q], z2 = z2src[q];
         if (z1 > NEG_HALF) {
             const int i = o1 + q;   // live cells lie inside the table: i >= 0
             P1[(uint32_t)i & (kRing - 1)] = z1 - G * d1;
@@ -2482,15 +2472,18 @@ __device__ void generic_start(const BatchDev &b, uint32_t coff, int gap, int *P1
     __syncthreads();   // s_rng read by every thread before another task resets it
 }
 
+// The ring phase of an unbounded extension, from the register window the
+// task's band outgrew (its state in xs, its anti-diagonals in z1 / z2).
 template <bool COUNT>
-__device__ void generic_run(const BatchDev &b, uint32_t coff, const uint32_t *__restrict__ W, const Geo &g, int X,
-                            int ma, int mi, int gap, int *ring, int *G2, int *G1, int *G0,
-                            GPart (*part)[kGenericWaves], TaskOut &o)
+__device__ void generic_run(const uint32_t *__restrict__ W, const Geo &g, int X, int ma, int mi, int gap,
+                            const XState &xs, const int *z1, const int *z2, int win, int *ring, int *G2, int *G1,
+                            int *G0, GPart (*part)[kGenericWaves], TaskOut &o)
 {
     const int tid = threadIdx.x;
     GState s;
     int *P0 = ring, *P1 = ring + kRing, *P2 = ring + 2 * kRing;
-    generic_start(b, coff, gap, P1, P2, s);
+    s.d = xs.d; s.T = xs.T; s.bi = xs.bi; s.bj = xs.bj; s.cells = xs.cells; s.slots = xs.slots;
+    generic_resume(z1, z2, win, xs.base, gap, P1, P2, s);
     if (!generic_diags<COUNT, true>(W, g, X, ma, mi, gap, P2, P1, P0, s, part)) {
         // the band outgrew the ring: the live cells of the last two
         // anti-diagonals move to global memory
@@ -2503,16 +2496,25 @@ __device__ void generic_run(const BatchDev &b, uint32_t coff, const uint32_t *__
     o.score = s.T; o.i = s.bi; o.j = s.bj; o.status = (uint32_t)kGenericClass; o.cells = s.cells; o.slots = s.slots;
 }
 
+// Unbounded class.  Each extension first runs in a register window of
+// kGenericWin slots shared by the workgroup's 16 wavefronts (4 cells per
+// lane), resumed from the 2048-slot class's carried state; a band that
+// outgrows it continues in the LDS ring (and in global memory beyond it).
+constexpr int kGenericWin = 4096;
+constexpr int kGenericC = kGenericWin / (64 * kGenericWaves);
+
 template <bool COUNT>
 __global__ void __launch_bounds__(kGenericThreads) generic_kernel(BatchDev b, StoreDev st, int32_t *scratch,
                                                                   uint64_t stride)
 {
     __shared__ int ring[3 * kRing];
     __shared__ GPart part[2][kGenericWaves];
+    __shared__ GroupShared<kGenericWaves, kGenericWin> gsh;
     __shared__ uint32_t s_task;
     const uint32_t qcap = 2u * b.cap;
     const int cls = kGenericClass;
     const uint32_t cnt = b.ctr[CtrLayout::kCount + cls];
+    const int wv = uni((int)(threadIdx.x >> 6));
     int *base = scratch + (uint64_t)blockIdx.x * 3 * stride;
     for (;;) {
         if (threadIdx.x == 0) s_task = atomicAdd(&b.ctr[CtrLayout::kHead + cls], 1u);
@@ -2520,14 +2522,27 @@ __global__ void __launch_bounds__(kGenericThreads) generic_kernel(BatchDev b, St
         const uint32_t idx = s_task;
         __syncthreads();         // read by every thread before thread 0 writes it again
         if (idx >= cnt) break;   // uniform over the block
-        const uint32_t t = b.qbuf[cls * qcap + idx];
-        const uint32_t coff = b.qstate[cls * qcap + idx];
+        const uint32_t t = (uint32_t)uni((int)b.qbuf[cls * qcap + idx]);
+        const uint32_t coff = (uint32_t)uni((int)b.qstate[cls * qcap + idx]);
         const Task k = load_task(b.recs, st.reads, t);
+        XState xs;
+        uint32_t stt;
+        if (k.ma != 1)
+            stt = group_run<kGenericC, kGenericWaves, COUNT, false, false>(b, st, k, gsh, wv, xs, coff);
+        else if (sigma_fits_2bits(k))
+            stt = group_run<kGenericC, kGenericWaves, COUNT, true, true>(b, st, k, gsh, wv, xs, coff);
+        else
+            stt = group_run<kGenericC, kGenericWaves, COUNT, true, false>(b, st, k, gsh, wv, xs, coff);
         TaskOut o;
-        generic_run<COUNT>(b, coff, st.words, k.g, k.x, k.ma, k.mi, k.gap, ring, base, base + stride,
-                           base + 2 * stride, part, o);
+        if (stt == kDone) {
+            o.score = xs.T; o.i = xs.bi; o.j = xs.bj; o.status = (uint32_t)cls; o.cells = xs.cells;
+            o.slots = xs.slots;
+        } else {
+            generic_run<COUNT>(st.words, k.g, k.x, k.ma, k.mi, k.gap, xs, gsh.win, gsh.win + kGenericWin,
+                               kGenericWin, ring, base, base + stride, base + 2 * stride, part, o);
+        }
         if (threadIdx.x == 0) b.tout[t] = o;
-        __syncthreads();         // ring and scratch of this task no longer read before the next one starts
+        __syncthreads();         // ring, window and scratch of this task no longer read before the next one starts
     }
 }
 

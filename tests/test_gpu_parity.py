@@ -172,6 +172,53 @@ def test_unbounded_resume_into_used_ring(xd):
     assert_same(res, cells, ref)
 
 
+def test_unbounded_window_then_ring(xd):
+    # Unrelated 12-20 kb reads at X = 800-3000: widest bands of 3,300-8,400
+    # cells with dead cells inside.  The unbounded class starts each
+    # extension in its 4096-slot register window (resumed from the 2048-slot
+    # class); bands past 4092 move into the LDS ring, those past 8192 on to
+    # global memory.  One workgroup runs every task in turn, so each resume
+    # lands in buffers an earlier task used.
+    rng = np.random.Generator(np.random.PCG64(93))
+    lens = rng.integers(12000, 20001, size=10)
+    codes = rng.integers(0, 4, int(lens.sum())).astype(np.uint8)
+    store = W.ReadStore(codes, np.concatenate([[0], np.cumsum(lens)[:-1]]), lens)
+    n = 6
+    recs = np.zeros(n, W.RECORD_DTYPE)
+    recs["read_a"] = np.arange(n)
+    recs["read_b"] = np.arange(n) + 4
+    recs["pos_a"] = rng.integers(0, 3000, n)
+    recs["pos_b"] = rng.integers(0, 3000, n)
+    recs["k"] = 5
+    recs["strand"] = [0, 1, 0, 1, 0, 1]
+    recs["x"] = [800, 1500, 3000, 800, 1500, 4000]
+    order = np.argsort(-lens)   # the last record: the two longest reads, seeds at 0
+    recs["read_a"][5], recs["read_b"][5], recs["pos_a"][5], recs["pos_b"][5], recs["strand"][5] = \
+        order[0], order[1], 0, 0, 0
+    recs["match"], recs["mismatch"], recs["gap"] = 1, -1, -1
+    widths = []
+    for R in recs:
+        a, b = store.read(int(R["read_a"])), store.read(int(R["read_b"]))
+        k, pa, pb = int(R["k"]), int(R["pos_a"]), int(R["pos_b"])
+        if R["strand"]:
+            b = W.revcomp_codes(b)
+            pb = b.size - pb - k
+        for u, v in ((a[:pa][::-1], b[:pb][::-1]), (a[pa + k:], b[pb + k:])):
+            widths.append(oracle.extend_band(u.copy(), v.copy(), 1, -1, -1, int(R["x"]))[1])
+    widths = np.array(widths)
+    # the case holds bands for the window, the ring and global memory
+    assert np.any((widths > 2175) & (widths < 3900)) and np.any((widths > 4300) & (widths < 7800)) \
+        and np.any(widths > 8600), widths
+    ref, _ = oracle.batch(store.codes, store.off, store.length, recs)
+    note("unbounded class: register window, then LDS ring and global memory (12-20 kb, X = 800-4000)")
+    for gw in (16, 4096):
+        with xd.Context(store) as ctx:
+            ctx.set_tuning(generic_waves=gw)
+            res, cells, st = ctx.run(recs, count_cells=True)
+        assert_same(res, cells, ref)
+        assert int(st["stage_tasks"][xd.STAGE_NAMES.index("generic")]) == int(np.sum(widths > 2044))
+
+
 @pytest.mark.parametrize("wide_waves", [1, 2, 4])
 def test_class_hand_over_pool_overflow(xd, wide_waves):
     # Every right extension here outgrows the 1024- and 2048-slot windows
