@@ -72,8 +72,10 @@ __device__ __forceinline__ uint32_t codes16_at(const uint32_t *__restrict__ W, u
 }
 
 // Guard of the store: reads keep at least kGuardWords words (8192 bases) before
-// their first and after their last base, so a lane's code window -- which
-// starts within 2 windows + 64 bases of its sequence -- never leaves the store.
+// their first and after their last base.  A window always holds its live
+// band, so a lane's code window reaches at most one window width (4096 slots
+// at most) plus one block of codes past either end of its sequence and never
+// leaves the store.
 constexpr int kGuardWords = 512;
 
 // 16*NW codes starting at code p of a sequence whose first base sits at bit
