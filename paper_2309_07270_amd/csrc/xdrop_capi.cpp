@@ -37,6 +37,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "xdrop_admission.h"
 #include "xdrop_internal.h"
 
 
@@ -610,43 +611,34 @@ Slot *new_slot(xdrop_ctx *c)
 // waiters.  Throws when an allocation fails (the slot involved is left empty).
 Slot *try_admit(xdrop_ctx *c, size_t n)
 {
-    Slot *best = nullptr;
-    for (auto &s : c->slots)
-        if (!s->busy && s->cap >= n && (!best || s->cap < best->cap)) best = s.get();
-    if (best) return best;
+    std::vector<SlotView> view;
+    for (auto &s : c->slots) view.push_back(SlotView{s->busy, s->cap, s->bytes});
     const uint32_t cap = round_cap(n);
     const size_t need = slot_footprint(c, cap);
-    // a new slot
-    if (c->slots.size() < c->max_inflight && c->used + need <= c->budget) {
+    const AdmitPlan p = plan_admission(view, (uint32_t)n, need, c->used, c->budget, c->max_inflight);
+    switch (p.kind) {
+    case AdmitPlan::kReuse:
+        return c->slots[p.slot].get();
+    case AdmitPlan::kNew: {
         Slot *s = new_slot(c);
         alloc_slot_buffers(c, *s, cap);
         c->used += s->bytes;
         return s;
     }
-    // re-size idle slots: empty them, largest first, until the batch fits;
-    // nothing is released unless that makes room
-    std::vector<Slot *> idle;
-    size_t idle_bytes = 0;
-    for (auto &s : c->slots)
-        if (!s->busy) {
-            idle.push_back(s.get());
-            idle_bytes += s->bytes;
+    case AdmitPlan::kResize: {
+        for (int k : p.release) {
+            c->used -= c->slots[k]->bytes;
+            free_slot_buffers(*c->slots[k]);
         }
-    if (idle.empty() || c->used - idle_bytes + need > c->budget) return nullptr;
-    std::sort(idle.begin(), idle.end(), [](const Slot *a, const Slot *b) { return a->bytes > b->bytes; });
-    Slot *target = idle[0];
-    for (Slot *s : idle) {
-        if (c->used + need <= c->budget) break;
-        c->used -= s->bytes;
-        free_slot_buffers(*s);
+        Slot *target = c->slots[p.slot].get();
+        alloc_slot_buffers(c, *target, cap);
+        c->used += target->bytes;
+        return target;
     }
-    if (target->cap) {   // the largest idle slot was not needed for room: empty it too, it is re-sized
-        c->used -= target->bytes;
-        free_slot_buffers(*target);
+    case AdmitPlan::kNone:
+        break;
     }
-    alloc_slot_buffers(c, *target, cap);
-    c->used += target->bytes;
-    return target;
+    return nullptr;
 }
 
 xdrop_status submit_common(xdrop_ctx *c, std::shared_ptr<Ticket> t, const xdrop_record *host_recs,
