@@ -68,7 +68,7 @@ typedef struct {
     int32_t device;               /* HIP device ordinal                     */
     uint32_t mode;                /* XDROP_MODE_*                           */
     uint32_t max_inflight;        /* batches admitted at once; 0 -> 4       */
-    uint64_t hbm_budget_bytes;    /* device bytes for in-flight batches; 0 -> 8 GiB */
+    uint64_t hbm_budget_bytes;    /* device bytes for in-flight batches; 0 -> 32 GiB */
     const char *tuning_cache;     /* path of the autotuner cache, or NULL   */
     uint32_t flags;               /* XDROP_FLAG_*                           */
 } xdrop_config;

@@ -46,6 +46,10 @@ using namespace xd;
 namespace {
 
 constexpr uint32_t kPlainChunk = 10000;
+// admission budget when the caller gives none: room for a 4M-record batch
+// (about 9.5 GB with its 8 GiB carry pool) and slots of the serving loop
+// beside it, a ninth of one MI355X's 288 GB
+constexpr uint64_t kDefaultBudget = 32ull << 30;
 constexpr uint64_t kGuardBases = 8192 + 64;   // unused bases before and after the store (kernel loads reach 8192 bases past a read)
 
 using clk = std::chrono::steady_clock;
@@ -127,7 +131,7 @@ struct xdrop_ctx {
     int device = 0;
     uint32_t mode = XDROP_MODE_PERSISTENT;
     uint32_t max_inflight = 4;
-    uint64_t budget = 8ull << 30;
+    uint64_t budget = kDefaultBudget;
     uint64_t used = 0;
     int cus = 256;
     bool profile = false;
@@ -246,15 +250,16 @@ bool validate_host(const xdrop_ctx *c, const xdrop_record &R, std::string &why)
     return true;
 }
 
-// carry pool of a slot: 512 words per record of capacity, at most 1 Gi words
-// (4 GiB).  The c4 stress mix hands about 0.16 extensions per record to the
-// 2048-slot class, 2,064 words each (330 words per record), plus a few to
-// the unbounded kernel; a full pool only makes the remaining hand-overs
-// restart from the seed, which repeats most of an extension in a window far
+// carry pool of a slot: 1024 words per record of capacity, at most 2 Gi
+// words (8 GiB).  The c4 stress mix hands about 0.9 extensions per record
+// from the adaptive to the first wide class (528 words each: a 256-slot
+// window) and 0.04 from the first wide class on (2,576 words each), about
+// 570 words per record; a full pool only makes the remaining hand-overs
+// restart from the seed, which repeats an extension's start in a window far
 // wider than its early band
 uint32_t carry_words_for(uint32_t cap)
 {
-    return (uint32_t)std::min<uint64_t>((uint64_t)cap * 512u, 1ull << 30);
+    return (uint32_t)std::min<uint64_t>((uint64_t)cap * 1024u, 1ull << 31);
 }
 
 size_t slot_bytes(uint32_t cap)
@@ -905,7 +910,7 @@ xdrop_status xdrop_batch_create(const xdrop_config *cfg, xdrop_ctx **out)
     c->device = cfg->device;
     c->mode = cfg->mode;
     c->max_inflight = cfg->max_inflight ? cfg->max_inflight : 4;
-    c->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (8ull << 30);
+    c->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : kDefaultBudget;
     c->profile = (cfg->flags & XDROP_FLAG_PROFILE) != 0;
     c->tune = default_tuning();
     if (cfg->tuning_cache) {

@@ -851,7 +851,7 @@ __device__ __forceinline__ int fit_c(int width, int margin)
 // next class).
 template <bool COUNT, bool MA1, bool SIGF>
 __device__ bool run_adaptive(const uint32_t *__restrict__ W, const Task &k, int *lds, XState &s,
-                             int grow_margin, int shrink_margin)
+                             int grow_margin, int shrink_margin, int &win_out)
 {
     // margins >= 2: a band that was just narrowed fits its new window with
     // two free slots per side (an edge slot plus one pair), so it cannot be
@@ -893,7 +893,10 @@ __device__ bool run_adaptive(const uint32_t *__restrict__ W, const Task &k, int 
         if (st == kGrow) {
             nc = fit_c(width, grow_margin);
             if (nc == 0) nc = fit_c(width, 2);
-            if (nc == 0) return false;
+            if (nc == 0) {
+                win_out = 64 * C;   // the window run() saved to LDS
+                return false;
+            }
         } else {
             nc = C - 1;
         }
@@ -1489,45 +1492,6 @@ __global__ void __launch_bounds__(256) narrow_kernel(BatchDev b, StoreDev st, in
     }
 }
 
-// Class 1: adaptive windows.  Tasks whose band outgrows 256 cells go to the
-// first wide class.  Registers capped for 6 wavefronts per SIMD (the
-// compiler's own choice allows 5; the cap costs one spill at entry and its
-// reload per task).
-template <bool COUNT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) adaptive_kernel(BatchDev b, StoreDev st, int grow_margin, int shrink_margin)
-{
-    __shared__ int lds_all[4][2 * WMAX];
-    int *lds = lds_all[threadIdx.x >> 6];
-    const int cls = kAdaptiveClass;
-    const uint32_t qcap = 2u * b.cap;
-    const uint32_t cnt = b.ctr[CtrLayout::kCount + cls];
-    for (;;) {
-        const uint32_t idx = wave_fetch_add(&b.ctr[CtrLayout::kHead + cls], 1u);
-        if (idx >= cnt) break;
-        const uint32_t t = (uint32_t)uni((int)b.qbuf[cls * qcap + idx]);
-        const Task k = load_task(b.recs, st.reads, t);
-        XState s;
-        bool ok;
-        if (k.ma != 1)
-            ok = run_adaptive<COUNT, false, false>(st.words, k, lds, s, grow_margin, shrink_margin);
-        else if (sigma_fits_2bits(k))
-            ok = run_adaptive<COUNT, true, true>(st.words, k, lds, s, grow_margin, shrink_margin);
-        else
-            ok = run_adaptive<COUNT, true, false>(st.words, k, lds, s, grow_margin, shrink_margin);
-        if (ok) {
-            TaskOut o;   // every lane stores the same (wave-uniform) values
-            o.score = s.T; o.i = s.bi; o.j = s.bj; o.status = (uint32_t)cls; o.cells = s.cells; o.slots = s.slots;
-            b.tout[t] = o;
-        } else {
-            // restarts in the first wide class (adaptive bands reach 256
-            // slots early in an extension, so little work is repeated)
-            const uint32_t pos = wave_fetch_add(&b.ctr[CtrLayout::kCount + cls + 1], 1u);
-            b.qbuf[(cls + 1) * qcap + pos] = t;
-            b.qstate[(cls + 1) * qcap + pos] = kNoCarry;
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Hand-over between classes.  A wide window that overflows stores its state
 // in the carry pool, and the next class resumes from it instead of
@@ -1587,6 +1551,68 @@ __device__ __forceinline__ void carry_state(const int32_t *rec, XState &s)
               ((uint64_t)(uint32_t)carry_word(rec, CarryLayout::kSlots + 1) << 32);
 }
 
+// A task whose band outgrew class cls: its window (saved in LDS, win slots
+// per anti-diagonal at the given stride) and state go to the carry pool and
+// the task to the next class's queue.  When the pool is full the task
+// restarts there from the seed.
+template <bool COUNT>
+__device__ void carry_out(const BatchDev &b, uint32_t t, int cls, const XState &s, const int *lds, int win,
+                          int stride)
+{
+    const uint32_t qcap = 2u * b.cap;
+    const uint32_t off = carry_alloc(b, CarryLayout::kHeader + 2 * (uint32_t)win);
+    if (off != kNoCarry) carry_store(b, off, s, lds, win, stride);
+    const uint32_t pos = wave_fetch_add(&b.ctr[CtrLayout::kCount + cls + 1], 1u);
+    b.qbuf[(cls + 1) * qcap + pos] = t;
+    b.qstate[(cls + 1) * qcap + pos] = off;
+    if (COUNT && off != kNoCarry && lane_id() == 0) {
+        // the carried state keeps the task's running cell and slot-step
+        // totals, which the class that completes it reports: credit this
+        // class with what it computed so far and debit the next one the same
+        // (modulo 2^64), so that each stage's sums hold only its own work
+        const int stg = 1 + cls;
+        atomicAdd(&b.stage_sum[stg], (unsigned long long)s.cells);
+        atomicAdd(&b.stage_sum[stg + 1], 0ull - (unsigned long long)s.cells);
+        atomicAdd(&b.stage_sum[16 + stg], (unsigned long long)s.slots);
+        atomicAdd(&b.stage_sum[16 + stg + 1], 0ull - (unsigned long long)s.slots);
+    }
+}
+
+// Class 1: adaptive windows.  A task whose band outgrows 256 cells hands its
+// window and state to the first wide class, which resumes it.  Registers
+// capped for 6 wavefronts per SIMD (the compiler's own choice allows 5).
+template <bool COUNT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) adaptive_kernel(BatchDev b, StoreDev st, int grow_margin, int shrink_margin)
+{
+    __shared__ int lds_all[4][2 * WMAX];
+    int *lds = lds_all[threadIdx.x >> 6];
+    const int cls = kAdaptiveClass;
+    const uint32_t qcap = 2u * b.cap;
+    const uint32_t cnt = b.ctr[CtrLayout::kCount + cls];
+    for (;;) {
+        const uint32_t idx = wave_fetch_add(&b.ctr[CtrLayout::kHead + cls], 1u);
+        if (idx >= cnt) break;
+        const uint32_t t = (uint32_t)uni((int)b.qbuf[cls * qcap + idx]);
+        const Task k = load_task(b.recs, st.reads, t);
+        XState s;
+        bool ok;
+        int win = 0;
+        if (k.ma != 1)
+            ok = run_adaptive<COUNT, false, false>(st.words, k, lds, s, grow_margin, shrink_margin, win);
+        else if (sigma_fits_2bits(k))
+            ok = run_adaptive<COUNT, true, true>(st.words, k, lds, s, grow_margin, shrink_margin, win);
+        else
+            ok = run_adaptive<COUNT, true, false>(st.words, k, lds, s, grow_margin, shrink_margin, win);
+        if (ok) {
+            TaskOut o;   // every lane stores the same (wave-uniform) values
+            o.score = s.T; o.i = s.bi; o.j = s.bj; o.status = (uint32_t)cls; o.cells = s.cells; o.slots = s.slots;
+            b.tout[t] = o;
+        } else {
+            carry_out<COUNT>(b, t, cls, s, lds, win, WMAX);
+        }
+    }
+}
+
 // Window widths (cells per lane) of the two wide classes.  Each class widens
 // and narrows its window along its ladder as the band changes, handing the
 // band over through LDS as the adaptive kernel does; its widest window is
@@ -1633,9 +1659,8 @@ __device__ uint32_t run_ladder(const BatchDev &b, const StoreDev &st, const Task
     out_off = kNoCarry;
     int ci = 0, from_win = 0, delta = 0;
     bool fresh = true;
-    // the first wide class takes tasks from the adaptive kernel, which hands
-    // over no state: no resume code there (it would cost that kernel registers)
-    if (L > 0 && coff != kNoCarry) {
+    // a carried window is narrower than the widest rung, so some rung holds it
+    if (coff != kNoCarry) {
         const int32_t *rec = b.carry + coff;
         carry_state(rec, s);
         from_win = carry_word(rec, CarryLayout::kWin);   // a narrower class's window: fits this stride
