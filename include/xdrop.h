@@ -80,12 +80,12 @@ enum {
 
 /* Kernel stages reported in xdrop_batch_stats.stage_ms / stage_cells.  An
  * extension with a small drop (x <= the narrow_x tuning knob, persistent
- * form) and weights match 1, gap -1, mismatch 0, -1 or -2 runs in the narrow
- * kernel first; every other one in the adaptive kernel.  It moves to the
- * next stage only when its live band outgrows the current one: out of the
- * narrow and adaptive kernels it restarts from the seed; between the later
- * stages it carries its state over (restarting only when the batch's carry
- * pool is full). */
+ * form, batches of at least narrow_min_records records) and weights match 1,
+ * gap -1, mismatch 0, -1 or -2 runs in the narrow kernel first; every other
+ * one in the adaptive kernel.  It moves to the next stage only when its live
+ * band outgrows the current one: out of the narrow kernel it restarts from
+ * the seed; from the adaptive kernel on it carries its state over
+ * (restarting only when the batch's carry pool is full). */
 enum {
     XDROP_STAGE_INGEST = 0,       /* counter reset, validation, seed, bucketing  */
     XDROP_STAGE_NARROW = 1,       /* two extensions per wavefront, windows of
@@ -94,10 +94,14 @@ enum {
                                      follows the band width                 */
     XDROP_STAGE_WIDE1280 = 3,     /* register window of 512..1280 slots that
                                      follows the band width                 */
-    XDROP_STAGE_WIDE2048 = 4,     /* register window of 1536..2048 slots    */
-    XDROP_STAGE_GENERIC = 5,      /* unbounded band: one workgroup per
-                                     extension, LDS ring (global memory for
-                                     bands over 8192 cells)                 */
+    XDROP_STAGE_WIDE2048 = 4,     /* register window of 2048 slots, shared by
+                                     the wide_waves wavefronts of a workgroup
+                                     (one wavefront: 1536..2048 slots)      */
+    XDROP_STAGE_GENERIC = 5,      /* unbounded band: one 16-wavefront
+                                     workgroup per extension, a shared
+                                     4096-slot register window, then an LDS
+                                     ring (global memory for bands over 8192
+                                     cells)                                 */
     XDROP_STAGE_FINALIZE = 6,     /* result write-back                      */
     XDROP_NUM_STAGES = 7
 };
@@ -214,10 +218,12 @@ xdrop_status xdrop_set_tuning(xdrop_ctx *c, const xdrop_tuning *t);
  * records) under launch parameters chosen by coordinate descent -- each knob
  * (persistent grid size, length bucketing, adaptive window margins, grid of
  * the unbounded-band kernel, drop bound of the two-extensions-per-wavefront
- * narrow stage) swept in turn with the others at the best so
- * far, two rounds, each setting timed by the better of two runs after a
- * warm-up -- keep the fastest by device time and make it the context's
- * tuning.  Every setting gives the same results.  When cache_path is non-NULL the choice is
+ * narrow stage, wavefronts per extension of the 2048-slot stage) swept in
+ * turn with the others at the best so far, two rounds, each setting timed by
+ * the better of two runs after a warm-up -- keep the fastest by device time
+ * and make it the context's tuning.  narrow_min_records is not swept (a
+ * sample is one batch size).  Every setting gives the same results.  When
+ * cache_path is non-NULL the choice is
  * written there (text, one "key value" per line) and later contexts created
  * with cfg->tuning_cache = cache_path start from it.  *best_ms (nullable)
  * gets the best device time.  Only while no batch is in flight. */
