@@ -3,11 +3,13 @@
 batched (persistent, graph-captured) vs plain (one launch sequence per
 10,000-record batch), with p50/p99 batch latency.
 
-Workload (default): 100,000 read pairs shaped like a 29x long-read E. coli set
-(4.6 Mb random genome, reads lognormal mean 8 kb / sd 4 kb clipped to
-[1, 30] kb, 15 % CLR-like error, one exact 17-mer seed per pair), X = 50,
-match +1 / mismatch -1 / gap -1, int32 scores.  Inputs are resident in HBM
-when the timed region starts.
+Workload (default, c2): 1,000,000 read pairs of uneven length shaped like a
+100x long-read E. coli set (4.6 Mb random genome, reads lognormal mean 10 kb
+/ sd 5 kb clipped to [1, 40] kb, 15 % CLR-like error, one exact 17-mer seed
+per pair), X drawn per pair from {20, 50, 100}, match +1 / mismatch -1 /
+gap -1, int32 scores, the whole batch in one captured graph.  --workload
+picks another preset (c0, c1, c4, c4b).  Inputs are resident in HBM when the
+timed region starts.
 
 A step is one pass of the whole hot path over the batch: record ingest
 (validation, orientation, seed score), left and right X-drop extensions,
