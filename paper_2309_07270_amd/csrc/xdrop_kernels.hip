@@ -1551,17 +1551,12 @@ __device__ __forceinline__ void carry_state(const int32_t *rec, XState &s)
               ((uint64_t)(uint32_t)carry_word(rec, CarryLayout::kSlots + 1) << 32);
 }
 
-// A task whose band outgrew class cls: its window (saved in LDS, win slots
-// per anti-diagonal at the given stride) and state go to the carry pool and
-// the task to the next class's queue.  When the pool is full the task
-// restarts there from the seed.
+// Task t moves from class cls to the next one's queue, with the carried
+// state at `off` (kNoCarry: none, it restarts there from the seed).
 template <bool COUNT>
-__device__ void carry_out(const BatchDev &b, uint32_t t, int cls, const XState &s, const int *lds, int win,
-                          int stride)
+__device__ void hand_over(const BatchDev &b, uint32_t t, int cls, const XState &s, uint32_t off)
 {
     const uint32_t qcap = 2u * b.cap;
-    const uint32_t off = carry_alloc(b, CarryLayout::kHeader + 2 * (uint32_t)win);
-    if (off != kNoCarry) carry_store(b, off, s, lds, win, stride);
     const uint32_t pos = wave_fetch_add(&b.ctr[CtrLayout::kCount + cls + 1], 1u);
     b.qbuf[(cls + 1) * qcap + pos] = t;
     b.qstate[(cls + 1) * qcap + pos] = off;
@@ -1576,6 +1571,18 @@ __device__ void carry_out(const BatchDev &b, uint32_t t, int cls, const XState &
         atomicAdd(&b.stage_sum[16 + stg], (unsigned long long)s.slots);
         atomicAdd(&b.stage_sum[16 + stg + 1], 0ull - (unsigned long long)s.slots);
     }
+}
+
+// A task whose band outgrew class cls: its window (saved in LDS, win slots
+// per anti-diagonal at the given stride) and state go to the carry pool when
+// it has room, and the task to the next class.
+template <bool COUNT>
+__device__ void carry_out(const BatchDev &b, uint32_t t, int cls, const XState &s, const int *lds, int win,
+                          int stride)
+{
+    const uint32_t off = carry_alloc(b, CarryLayout::kHeader + 2 * (uint32_t)win);
+    if (off != kNoCarry) carry_store(b, off, s, lds, win, stride);
+    hand_over<COUNT>(b, t, cls, s, off);
 }
 
 // Class 1: adaptive windows.  A task whose band outgrows 256 cells hands its
@@ -1758,21 +1765,7 @@ wide_kernel(BatchDev b, StoreDev st, int cls)
             o.score = s.T; o.i = s.bi; o.j = s.bj; o.status = (uint32_t)cls; o.cells = s.cells; o.slots = s.slots;
             b.tout[t] = o;
         } else {
-            const uint32_t pos = wave_fetch_add(&b.ctr[CtrLayout::kCount + cls + 1], 1u);
-            b.qbuf[(cls + 1) * qcap + pos] = t;
-            b.qstate[(cls + 1) * qcap + pos] = out_off;
-            if (COUNT && out_off != kNoCarry && lane_id() == 0) {
-                // the carried state keeps the task's running cell and
-                // slot-step totals, which the class that completes it
-                // reports: credit this class with what it computed so far
-                // and debit the next one the same (modulo 2^64), so that
-                // each stage's sums hold only its own work
-                const int stg = 1 + cls;
-                atomicAdd(&b.stage_sum[stg], (unsigned long long)s.cells);
-                atomicAdd(&b.stage_sum[stg + 1], 0ull - (unsigned long long)s.cells);
-                atomicAdd(&b.stage_sum[16 + stg], (unsigned long long)s.slots);
-                atomicAdd(&b.stage_sum[16 + stg + 1], 0ull - (unsigned long long)s.slots);
-            }
+            hand_over<COUNT>(b, t, cls, s, out_off);
         }
     }
 }
@@ -1803,7 +1796,7 @@ struct GroupShared {
     int xch[2][W][2];         // per parity of d and wavefront: flags, edge cell
     int vmx[W];               // largest values on an improving anti-diagonal (weights other than match 1)
     int red[W][4];            // block-level reductions
-    uint32_t task[2];         // task taken by wavefront 0: queue index
+    uint32_t task;            // queue index taken by wavefront 0
 };
 
 template <int C, int W, bool COUNT, bool MA1, bool SIGF>
@@ -2216,10 +2209,10 @@ group_kernel(BatchDev b, StoreDev st, int cls)
     for (;;) {
         if (wv == 0) {
             const uint32_t idx = wave_fetch_add(&b.ctr[CtrLayout::kHead + cls], 1u);
-            if (lane_id() == 0) sh.task[0] = idx;
+            if (lane_id() == 0) sh.task = idx;
         }
         __syncthreads();
-        const uint32_t idx = (uint32_t)uni((int)sh.task[0]);
+        const uint32_t idx = (uint32_t)uni((int)sh.task);
         __syncthreads();         // read by every wavefront before wavefront 0 writes it again
         if (idx >= cnt) break;   // uniform over the workgroup
         const uint32_t t = (uint32_t)uni((int)b.qbuf[cls * qcap + idx]);
@@ -2240,19 +2233,7 @@ group_kernel(BatchDev b, StoreDev st, int cls)
                 b.tout[t] = o;
             } else {
                 // the window (saved by run) goes to the unbounded kernel
-                const uint32_t off = carry_alloc(b, CarryLayout::kHeader + 2 * kGroupWin);
-                if (off != kNoCarry) carry_store(b, off, s, sh.win, kGroupWin, kGroupWin);
-                const uint32_t pos = wave_fetch_add(&b.ctr[CtrLayout::kCount + cls + 1], 1u);
-                b.qbuf[(cls + 1) * qcap + pos] = t;
-                b.qstate[(cls + 1) * qcap + pos] = off;
-                if (COUNT && off != kNoCarry && lane_id() == 0) {
-                    // as in wide_kernel: each stage's sums hold only its own work
-                    const int stg = 1 + cls;
-                    atomicAdd(&b.stage_sum[stg], (unsigned long long)s.cells);
-                    atomicAdd(&b.stage_sum[stg + 1], 0ull - (unsigned long long)s.cells);
-                    atomicAdd(&b.stage_sum[16 + stg], (unsigned long long)s.slots);
-                    atomicAdd(&b.stage_sum[16 + stg + 1], 0ull - (unsigned long long)s.slots);
-                }
+                carry_out<COUNT>(b, t, cls, s, sh.win, kGroupWin, kGroupWin);
             }
         }
         __syncthreads();   // the shared window is read by wavefront 0 before the next task writes it
