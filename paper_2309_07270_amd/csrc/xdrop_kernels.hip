@@ -1799,14 +1799,14 @@ struct GroupShared {
     uint32_t task;            // queue index taken by wavefront 0
 };
 
-template <int C, int W, bool COUNT, bool MA1, bool SIGF>
+template <int C, int W, bool COUNT, bool MA1, bool SIGF, int WSLOTS = W * 64 * C>
 struct GroupWindow {
     static constexpr int SEG = 64 * C;   // slots per wavefront
     static constexpr int WIN = W * SEG;
-    static constexpr int STRIDE = WIN;
+    static constexpr int STRIDE = WSLOTS;   // shared LDS copy: sized for the widest window of the class
     static constexpr int NWC = (C + UMAX + 16) / 16;   // words of codes per lane and block
-    static_assert(WIN <= 4096, "a lane's code window stays within the store's guard");
-    using Shared = GroupShared<W, WIN>;
+    static_assert(WIN <= WSLOTS && WSLOTS <= 4096, "a lane's code window stays within the store's guard");
+    using Shared = GroupShared<W, WSLOTS>;
 
     int Z1[C], Z2[C];
     uint32_t mmo[C], mme[C];
@@ -2079,7 +2079,7 @@ struct GroupWindow {
     // control).  Returns kDone, or kGrow with the window saved to the shared
     // buffer and s.mn / s.mx set.
     __device__ uint32_t run(const uint32_t *__restrict__ Wd, const Geo &g, int X, int ma, int mi, int gap,
-                            XState &s)
+                            XState &s, int shrink_width = -1)
     {
         const int lane = lane_id();
         const int m = g.m, n = g.n;
@@ -2096,12 +2096,12 @@ struct GroupWindow {
             int mn, mx;
             if (!band(mn, mx)) break;                 // two dead anti-diagonals
             const int width = mx - mn + 1;
-            if (width + 4 > WIN) {
+            if (width + 4 > WIN || width <= shrink_width) {
                 save();
                 s.mn = mn;
                 s.mx = mx;
                 s.T = ti - G * s.d;
-                return kGrow;
+                return width + 4 > WIN ? kGrow : kShrink;
             }
             if (min(mn, WIN - 1 - mx) < kRecentre) {
                 const int delta = mn - (WIN - width) / 2;
@@ -2149,37 +2149,63 @@ struct GroupWindow {
     }
 };
 
-// One extension in the group window: fresh, or resumed from the state the
-// first wide class carried over.  Cell and slot-step counts are summed over
-// the wavefronts into wavefront 0's state.
-template <int C, int W, bool COUNT, bool MA1, bool SIGF>
+// One extension in a window shared by a workgroup: fresh, or resumed from
+// the state a narrower class carried over.  The window moves between two
+// widths, W x 64 x CLO and W x 64 x CHI slots, through the shared LDS copy
+// (CLO == CHI: one width): it widens when the band outgrows the narrower one
+// and narrows once the band fits it with 64 slots to spare per side.  Cell
+// and slot-step counts are summed over the wavefronts into every
+// wavefront's state.
+template <int CLO, int CHI, int W, bool COUNT, bool MA1, bool SIGF>
 __device__ uint32_t group_run(const BatchDev &b, const StoreDev &st, const Task &k,
-                              typename GroupWindow<C, W, COUNT, MA1, SIGF>::Shared &sh, int wv, XState &s,
-                              uint32_t coff)
+                              GroupShared<W, W * 64 * CHI> &sh, int wv, XState &s, uint32_t coff)
 {
-    GroupWindow<C, W, COUNT, MA1, SIGF> w;
-    w.sh = &sh;
-    w.wv = wv;
-    w.s0 = w.SEG * wv;
+    constexpr int WHI = W * 64 * CHI, WLO = W * 64 * CLO;
+    using Lo = GroupWindow<CLO, W, COUNT, MA1, SIGF, WHI>;
+    using Hi = GroupWindow<CHI, W, COUNT, MA1, SIGF, WHI>;
+    bool hi = CLO == CHI, fresh = true;
+    int from_win = 0, delta = 0;
     if (coff != kNoCarry) {
         const int32_t *rec = b.carry + coff;
         carry_state(rec, s);
-        const int from_win = carry_word(rec, CarryLayout::kWin);   // a narrower class's window
+        from_win = carry_word(rec, CarryLayout::kWin);   // a narrower class's window
         for (int q = (int)threadIdx.x; q < from_win; q += 64 * W) {
             sh.win[q] = rec[CarryLayout::kHeader + q];
-            sh.win[w.STRIDE + q] = rec[CarryLayout::kHeader + from_win + q];
+            sh.win[WHI + q] = rec[CarryLayout::kHeader + from_win + q];
         }
         __syncthreads();
         const int width = s.mx - s.mn + 1;
-        const int delta = s.mn - (w.WIN - width) / 2;
+        hi = hi || width + 2 * kWideGrowMargin > WLO;
+        delta = s.mn - ((hi ? WHI : WLO) - width) / 2;
         s.base += delta;
-        w.load(from_win, delta);
-    } else {
-        w.init(s);
+        fresh = false;
+        if (COUNT && wv != 0) { s.cells = 0; s.slots = 0; }   // wavefront 0 holds the carried totals
     }
-    if (COUNT && wv != 0) { s.cells = 0; s.slots = 0; }   // wavefront 0 holds the carried totals
-    const uint32_t stt = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, s);
+    uint32_t stt;
+    for (;;) {
+        if (hi) {
+            Hi w;
+            w.sh = &sh; w.wv = wv; w.s0 = w.SEG * wv;
+            if (fresh) w.init(s); else w.load(from_win, delta);
+            stt = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, s, CLO == CHI ? -1 : WLO - 2 * kWideShrinkMargin);
+        } else {
+            Lo w;
+            w.sh = &sh; w.wv = wv; w.s0 = w.SEG * wv;
+            if (fresh) w.init(s); else w.load(from_win, delta);
+            stt = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, s);
+        }
+        if (stt == kDone || (stt == kGrow && hi)) break;   // done, or out of the class (window saved)
+        // the other width: the band was saved to the shared copy by run()
+        fresh = false;
+        const int width = s.mx - s.mn + 1;
+        from_win = hi ? WHI : WLO;
+        hi = stt == kGrow;
+        delta = s.mn - ((hi ? WHI : WLO) - width) / 2;
+        s.base += delta;
+    }
     if (COUNT) {
+        Hi w;
+        w.sh = &sh; w.wv = wv;
         w.publish((int)(uint32_t)s.cells, (int)(uint32_t)(s.cells >> 32), (int)(uint32_t)s.slots,
                   (int)(uint32_t)(s.slots >> 32));
         uint64_t c = 0, sl = 0;
@@ -2197,12 +2223,12 @@ __device__ uint32_t group_run(const BatchDev &b, const StoreDev &st, const Task 
 
 // The second wide class with W wavefronts per extension, one workgroup per
 // extension; wavefront 0 takes the tasks and writes results and hand-overs.
-template <int C, int W, bool COUNT>
+template <int CLO, int CHI, int W, bool COUNT>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 2 ? 3 : 4)))
 group_kernel(BatchDev b, StoreDev st, int cls)
 {
     __shared__ GroupShared<W, kGroupWin> sh;
-    static_assert(64 * C * W == kGroupWin, "one window width: the class limit");
+    static_assert(64 * CHI * W == kGroupWin, "the widest window is the class limit");
     const int wv = uni((int)(threadIdx.x >> 6));
     const uint32_t qcap = 2u * b.cap;
     const uint32_t cnt = b.ctr[CtrLayout::kCount + cls];
@@ -2221,11 +2247,11 @@ group_kernel(BatchDev b, StoreDev st, int cls)
         XState s;
         uint32_t status;
         if (k.ma != 1)
-            status = group_run<C, W, COUNT, false, false>(b, st, k, sh, wv, s, coff);
+            status = group_run<CLO, CHI, W, COUNT, false, false>(b, st, k, sh, wv, s, coff);
         else if (sigma_fits_2bits(k))
-            status = group_run<C, W, COUNT, true, true>(b, st, k, sh, wv, s, coff);
+            status = group_run<CLO, CHI, W, COUNT, true, true>(b, st, k, sh, wv, s, coff);
         else
-            status = group_run<C, W, COUNT, true, false>(b, st, k, sh, wv, s, coff);
+            status = group_run<CLO, CHI, W, COUNT, true, false>(b, st, k, sh, wv, s, coff);
         if (wv == 0) {
             if (status == kDone) {
                 TaskOut o;
@@ -2536,11 +2562,11 @@ __global__ void __launch_bounds__(kGenericThreads) generic_kernel(BatchDev b, St
         XState xs;
         uint32_t stt;
         if (k.ma != 1)
-            stt = group_run<kGenericC, kGenericWaves, COUNT, false, false>(b, st, k, gsh, wv, xs, coff);
+            stt = group_run<kGenericC, kGenericC, kGenericWaves, COUNT, false, false>(b, st, k, gsh, wv, xs, coff);
         else if (sigma_fits_2bits(k))
-            stt = group_run<kGenericC, kGenericWaves, COUNT, true, true>(b, st, k, gsh, wv, xs, coff);
+            stt = group_run<kGenericC, kGenericC, kGenericWaves, COUNT, true, true>(b, st, k, gsh, wv, xs, coff);
         else
-            stt = group_run<kGenericC, kGenericWaves, COUNT, true, false>(b, st, k, gsh, wv, xs, coff);
+            stt = group_run<kGenericC, kGenericC, kGenericWaves, COUNT, true, false>(b, st, k, gsh, wv, xs, coff);
         TaskOut o;
         if (stt == kDone) {
             o.score = xs.T; o.i = xs.bi; o.j = xs.bj; o.status = (uint32_t)cls; o.cells = xs.cells;
@@ -2664,15 +2690,15 @@ static void launch_wide_c(const BatchDev &b, const StoreDev &st, int cls, uint32
         hipLaunchKernelGGL((wide_kernel<L, false>), dim3(blocks), dim3(256), lds, s, b, st, cls);
 }
 
-template <int C, int W>
+template <int CLO, int CHI, int W>
 static void launch_group_c(const BatchDev &b, const StoreDev &st, int cls, uint32_t grid_waves, bool count,
                            hipStream_t s)
 {
     const uint32_t blocks = (grid_waves + W - 1) / W;
     if (count)
-        hipLaunchKernelGGL((group_kernel<C, W, true>), dim3(blocks), dim3(64 * W), 0, s, b, st, cls);
+        hipLaunchKernelGGL((group_kernel<CLO, CHI, W, true>), dim3(blocks), dim3(64 * W), 0, s, b, st, cls);
     else
-        hipLaunchKernelGGL((group_kernel<C, W, false>), dim3(blocks), dim3(64 * W), 0, s, b, st, cls);
+        hipLaunchKernelGGL((group_kernel<CLO, CHI, W, false>), dim3(blocks), dim3(64 * W), 0, s, b, st, cls);
 }
 
 void launch_wide(int which, const BatchDev &b, const StoreDev &st, uint32_t cus, int ext_waves, bool count_cells,
@@ -2681,8 +2707,8 @@ void launch_wide(int which, const BatchDev &b, const StoreDev &st, uint32_t cus,
     static_assert(kWideClasses == 2, "wide classes");
     const int cls = kAdaptiveClass + 1 + which;
     if (which == 0) launch_wide_c<0>(b, st, cls, cus * 8u, count_cells, s);
-    else if (ext_waves == 2) launch_group_c<16, 2>(b, st, cls, cus * 12u, count_cells, s);
-    else if (ext_waves == 4) launch_group_c<8, 4>(b, st, cls, cus * 16u, count_cells, s);
+    else if (ext_waves == 2) launch_group_c<12, 16, 2>(b, st, cls, cus * 12u, count_cells, s);
+    else if (ext_waves == 4) launch_group_c<6, 8, 4>(b, st, cls, cus * 16u, count_cells, s);
     else launch_wide_c<1>(b, st, cls, cus * 8u, count_cells, s);
 }
 
