@@ -1626,21 +1626,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) a
 // the class limit (kWideC).
 template <int L> struct WideLadder;
 template <> struct WideLadder<0> {
-    static constexpr int N = 4;
-    static constexpr int C0 = 8, C1 = 12, C2 = 16, C3 = 20;
+    static constexpr int N = 5;   // C = 8, 10, 12, 16, 20: 512..1280 slots
+    static constexpr __host__ __device__ int c(int ci) { return ci < 3 ? 8 + 2 * ci : 16 + 4 * (ci - 3); }
 };
 template <> struct WideLadder<1> {
-    static constexpr int N = 2;
-    static constexpr int C0 = 24, C1 = 32, C2 = 32, C3 = 32;
+    static constexpr int N = 2;   // C = 24, 32: 1536, 2048 slots
+    static constexpr __host__ __device__ int c(int ci) { return ci == 0 ? 24 : 32; }
 };
-static_assert(WideLadder<0>::C3 == kWideC[0] && WideLadder<1>::C1 == kWideC[1], "class limits");
+static_assert(WideLadder<0>::c(WideLadder<0>::N - 1) == kWideC[0] &&
+              WideLadder<1>::c(WideLadder<1>::N - 1) == kWideC[1], "class limits");
 constexpr int kWideGrowMargin = 32;     // free slots per side after widening
 constexpr int kWideShrinkMargin = 64;   // narrow once the band fits the next smaller window with this slack
 
 template <int L>
 __device__ __forceinline__ int ladder_c(int ci)
 {
-    return ci == 0 ? WideLadder<L>::C0 : ci == 1 ? WideLadder<L>::C1 : ci == 2 ? WideLadder<L>::C2 : WideLadder<L>::C3;
+    return WideLadder<L>::c(ci);
 }
 
 // smallest rung whose window holds `width` slots with `margin` free on each side; -1 if none
@@ -1650,6 +1651,25 @@ __device__ __forceinline__ int ladder_fit(int width, int margin)
     for (int ci = 0; ci < WideLadder<L>::N; ++ci)
         if (width + 2 * margin <= 64 * ladder_c<L>(ci)) return ci;
     return -1;
+}
+
+// The run of rung ci of class L's ladder (rungs I and up; a chain of tests
+// that the compiler unrolls): a fresh window (only at rung 0) or one loaded
+// from the window saved in LDS.
+template <int L, int I, bool COUNT, bool MA1, bool SIGF>
+__device__ __forceinline__ uint32_t run_rung(int ci, bool fresh, const StoreDev &st, const Task &k, int *lds,
+                                             XState &s, int from_win, int delta, int shrink_width)
+{
+    if constexpr (I >= WideLadder<L>::N) {
+        return kDone;   // not reached: ci < N
+    } else {
+        if (ci == I) {
+            Window<WideLadder<L>::c(I), COUNT, MA1, SIGF, 64 * kWideC[L]> w;
+            if (I == 0 && fresh) w.init(s); else w.load(lds, from_win, delta);
+            return w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
+        }
+        return run_rung<L, I + 1, COUNT, MA1, SIGF>(ci, fresh, st, k, lds, s, from_win, delta, shrink_width);
+    }
 }
 
 // One extension in wide class L: fresh, or resumed from the state a
@@ -1687,28 +1707,7 @@ __device__ uint32_t run_ladder(const BatchDev &b, const StoreDev &st, const Task
     }
     for (;;) {
         const int shrink_width = ci > 0 ? 64 * ladder_c<L>(ci - 1) - 2 * kWideShrinkMargin : -1;
-        uint32_t stt = kDone;
-        if (ci == 0) {
-            Window<LD::C0, COUNT, MA1, SIGF, STRIDE> w;
-            if (fresh) w.init(s); else w.load(lds, from_win, delta);
-            stt = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
-        } else if (LD::N == 2 || ci == 1) {
-            Window<LD::C1, COUNT, MA1, SIGF, STRIDE> w;
-            w.load(lds, from_win, delta);
-            stt = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
-        } else if (LD::N == 3 || ci == 2) {
-            if constexpr (LD::N > 2) {
-                Window<LD::C2, COUNT, MA1, SIGF, STRIDE> w;
-                w.load(lds, from_win, delta);
-                stt = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
-            }
-        } else {
-            if constexpr (LD::N > 3) {
-                Window<LD::C3, COUNT, MA1, SIGF, STRIDE> w;
-                w.load(lds, from_win, delta);
-                stt = w.run(st.words, k.g, k.x, k.ma, k.mi, k.gap, lds, s, shrink_width);
-            }
-        }
+        const uint32_t stt = run_rung<L, 0, COUNT, MA1, SIGF>(ci, fresh, st, k, lds, s, from_win, delta, shrink_width);
         if (stt == kDone) return kDone;
         fresh = false;
         const int width = s.mx - s.mn + 1;
@@ -1785,8 +1784,8 @@ wide_kernel(BatchDev b, StoreDev st, int cls)
 // the wavefronts' largest values on improving anti-diagonals.  Block control
 // (band, re-centring, end cell, two dead anti-diagonals, hand-over) uses
 // group-wide reductions, so every wavefront takes every branch and every
-// barrier together.  The window has one width: a band that outgrows it goes
-// to the unbounded kernel with its state.
+// barrier together.  The window moves between two widths (group_run); a band
+// that outgrows the wider one goes to the unbounded kernel with its state.
 // ---------------------------------------------------------------------------
 constexpr int kGroupWin = 64 * kWideC[1];   // slots of the window (the class limit)
 
