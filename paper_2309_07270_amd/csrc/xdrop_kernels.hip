@@ -14,6 +14,8 @@
 //     control is wave-uniform and lives in SGPRs.  The narrow class (small
 //     drops) runs two extensions per wavefront, one per half of the lanes,
 //     with the per-half control in pairs of SGPRs and per-lane thresholds;
+//     the 2048-slot class can share one window among the wavefronts of a
+//     workgroup (one segment each, an LDS exchange per anti-diagonal);
 //   * window kernels: the live band of anti-diagonals d-1 and d-2 is held in
 //     VGPRs, 64 lanes x C cells, indexed by slot s = C*lane + r with
 //     i = o_d + s and o_d = base + floor(d/2).  With that origin the diagonal
@@ -31,7 +33,8 @@
 //     runs unrolled without tests and is rerun with them if an edge slot went
 //     live.  A band that outgrows the window moves to a wider window through
 //     LDS, or to the next class, which resumes from its carried state;
-//   * unbounded kernel: one workgroup per extension, the last three
+//   * unbounded kernel: one workgroup per extension, first in a 4096-slot
+//     window shared by its wavefronts, then with the last three
 //     anti-diagonals in an LDS ring indexed by i (global memory for bands
 //     wider than the ring), any band width.
 #include <hip/hip_runtime.h>
@@ -847,8 +850,8 @@ __device__ __forceinline__ int fit_c(int width, int margin)
 
 // One extension with a window that widens and narrows with its band:
 // C = 1..4 cells per lane, the live band handed over through LDS.  Returns
-// false if the band outgrew the widest window (the task then restarts in the
-// next class).
+// false if the band outgrew the widest window; the window is then saved in
+// LDS (win_out slots per anti-diagonal) for the hand-over to the next class.
 template <bool COUNT, bool MA1, bool SIGF>
 __device__ bool run_adaptive(const uint32_t *__restrict__ W, const Task &k, int *lds, XState &s,
                              int grow_margin, int shrink_margin, int &win_out)
@@ -1732,8 +1735,8 @@ __device__ uint32_t run_ladder(const BatchDev &b, const StoreDev &st, const Task
 }
 
 // Wide class L for bands the adaptive kernel cannot hold.  The first class
-// (up to 1280 slots) runs 2 wavefronts per SIMD (256 VGPRs; the 1280-slot
-// rung costs a few spills at task entry); the second (up to 2048 slots)
+// (up to 1280 slots) runs 2 wavefronts per SIMD (256 VGPRs, a few spills at
+// task entry); the second, in this one-wavefront form (up to 2048 slots),
 // needs the whole register file and runs 1 per SIMD, so bands up to 1276
 // cells stay in the first.
 template <int L, bool COUNT>
